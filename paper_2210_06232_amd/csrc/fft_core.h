@@ -1,0 +1,312 @@
+// fft_core.h -- register/LDS Stockham FFT building blocks for gfx950 (wave64).
+//
+// A pencil of length N is held by T = N/E threads, E complex values each.  Thread t
+// always owns the positions t + T*m, m < E, both when it loads the pencil and when
+// it stores the transform, so a tile of pencils is read and written with the same
+// coalesced pattern.  Between radix stages the data are exchanged through LDS
+// (Stockham autosort: every stage reads at stride N/R and writes in expanded order,
+// so the output comes out in natural order with no bit reversal).
+//
+// Transforms are unnormalised: forward X[k] = sum_j x[j] exp(-2 pi i jk/N), inverse
+// with exp(+2 pi i jk/N) -- the DFT matrix of Sec. 2.3 of Wang & Jiang and N times
+// its inverse.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace eifp {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    T x, y;
+};
+
+template <typename T> __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T> __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T> __device__ __forceinline__ cpx<T> conj(cpx<T> a) { return {a.x, -a.y}; }
+template <typename T> __device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by i and by -i
+template <typename T> __device__ __forceinline__ cpx<T> muli(cpx<T> a) { return {-a.y, a.x}; }
+template <typename T> __device__ __forceinline__ cpx<T> mulmi(cpx<T> a) { return {a.y, -a.x}; }
+
+// cos(2 pi j / 48) for j = 0..12, correctly rounded; every in-register twiddle
+// exp(-+2 pi i e / R) with R | 48 is read off this quarter period.
+constexpr double kCos48q[13] = {
+    1.0, 0.9914448613738104, 0.9659258262890683, 0.9238795325112867,
+    0.8660254037844386, 0.7933533402912352, 0.7071067811865476, 0.6087614290087207,
+    0.5, 0.3826834323650898, 0.25881904510252074, 0.1305261922200516, 0.0};
+
+__host__ __device__ constexpr double cos48(int j) {
+    // j in [0, 48)
+    return j <= 12 ? kCos48q[j] : j <= 24 ? -kCos48q[24 - j] : j <= 36 ? -kCos48q[j - 24] : kCos48q[48 - j];
+}
+__host__ __device__ constexpr double sin48(int j) { return cos48((j + 36) % 48); }
+
+// v * exp(s 2 pi i e / R), s = -1 forward, +1 inverse; e and R are compile-time after
+// unrolling, so the branches fold and +-1, +-i cost no arithmetic.
+template <int R, bool INV, typename T>
+__device__ __forceinline__ cpx<T> twc(int e, cpx<T> v) {
+    e %= R;
+    if (e == 0) return v;
+    if ((4 * e) % R == 0) {
+        const int q = 4 * e / R;  // quarter turns
+        if (q == 2) return {-v.x, -v.y};
+        const bool plus_i = (q == 1) == INV;  // forward: q=1 -> -i
+        return plus_i ? muli(v) : mulmi(v);
+    }
+    const int j = (48 / R) * e;
+    const T c = (T)cos48(j);
+    const T s = INV ? (T)sin48(j) : (T)-sin48(j);
+    return {v.x * c - v.y * s, v.x * s + v.y * c};
+}
+
+// ---------------------------------------------------------------------------------
+// small DFTs in registers
+// ---------------------------------------------------------------------------------
+template <int R, bool INV, typename T> struct Dft;
+
+template <bool INV, typename T> struct Dft<1, INV, T> {
+    __device__ __forceinline__ static void run(cpx<T>*) {}
+};
+
+template <bool INV, typename T> struct Dft<2, INV, T> {
+    __device__ __forceinline__ static void run(cpx<T>* a) {
+        const cpx<T> t = a[0];
+        a[0] = t + a[1];
+        a[1] = t - a[1];
+    }
+};
+
+template <bool INV, typename T> struct Dft<3, INV, T> {
+    __device__ __forceinline__ static void run(cpx<T>* a) {
+        // w = exp(-+2 pi i/3) = -1/2 -+ i sqrt(3)/2
+        const T h = (T)0.8660254037844386;
+        const cpx<T> s = a[1] + a[2];
+        const cpx<T> d = a[1] - a[2];
+        const cpx<T> m = {a[0].x - (T)0.5 * s.x, a[0].y - (T)0.5 * s.y};
+        // i * sin * d with sin = -+sqrt(3)/2
+        const cpx<T> r = INV ? cpx<T>{-h * d.y, h * d.x} : cpx<T>{h * d.y, -h * d.x};
+        a[0] = a[0] + s;
+        a[1] = m + r;
+        a[2] = m - r;
+    }
+};
+
+template <bool INV, typename T> struct Dft<4, INV, T> {
+    __device__ __forceinline__ static void run(cpx<T>* a) {
+        const cpx<T> t0 = a[0] + a[2], t1 = a[0] - a[2];
+        const cpx<T> t2 = a[1] + a[3], t3 = a[1] - a[3];
+        const cpx<T> r = INV ? muli(t3) : mulmi(t3);
+        a[0] = t0 + t2;
+        a[2] = t0 - t2;
+        a[1] = t1 + r;
+        a[3] = t1 - r;
+    }
+};
+
+// Cooley-Tukey split R = R1 R2 in registers:
+//   X[k1 + R1 k2] = sum_n2 W_R2^{n2 k2} W_R^{n2 k1} sum_n1 x[R2 n1 + n2] W_R1^{n1 k1}
+template <int R1, int R2, bool INV, typename T>
+__device__ __forceinline__ void dft_split(cpx<T>* a) {
+    constexpr int R = R1 * R2;
+    cpx<T> y[R];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+        cpx<T> t[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) t[n1] = a[R2 * n1 + n2];
+        Dft<R1, INV, T>::run(t);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) y[n2 * R1 + k1] = twc<R, INV>(n2 * k1, t[k1]);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        cpx<T> t[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) t[n2] = y[n2 * R1 + k1];
+        Dft<R2, INV, T>::run(t);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) a[k1 + R1 * k2] = t[k2];
+    }
+}
+
+template <bool INV, typename T> struct Dft<6, INV, T> {
+    __device__ __forceinline__ static void run(cpx<T>* a) { dft_split<3, 2, INV, T>(a); }
+};
+template <bool INV, typename T> struct Dft<8, INV, T> {
+    __device__ __forceinline__ static void run(cpx<T>* a) { dft_split<4, 2, INV, T>(a); }
+};
+template <bool INV, typename T> struct Dft<12, INV, T> {
+    __device__ __forceinline__ static void run(cpx<T>* a) { dft_split<4, 3, INV, T>(a); }
+};
+template <bool INV, typename T> struct Dft<16, INV, T> {
+    __device__ __forceinline__ static void run(cpx<T>* a) { dft_split<4, 4, INV, T>(a); }
+};
+
+// ---------------------------------------------------------------------------------
+// plans: N = product of the stage radices, each radix divides E (values per thread)
+// ---------------------------------------------------------------------------------
+template <int N_, int E_, int... Rs>
+struct PlanDef {
+    static constexpr int N = N_, E = E_, T = N_ / E_, S = sizeof...(Rs);
+    static constexpr int R[S] = {Rs...};
+};
+
+template <int N, int E> struct Plan;
+#define EIFP_PLAN(N, E, ...) \
+    template <> struct Plan<N, E> : PlanDef<N, E, __VA_ARGS__> {};
+EIFP_PLAN(2, 2, 2)
+EIFP_PLAN(3, 3, 3)
+EIFP_PLAN(4, 4, 4)
+EIFP_PLAN(6, 6, 6)
+EIFP_PLAN(8, 8, 8)
+EIFP_PLAN(12, 12, 12)
+EIFP_PLAN(12, 6, 6, 2)
+EIFP_PLAN(16, 16, 16)
+EIFP_PLAN(16, 8, 8, 2)
+EIFP_PLAN(16, 4, 4, 4)
+EIFP_PLAN(24, 12, 12, 2)
+EIFP_PLAN(24, 6, 6, 2, 2)
+EIFP_PLAN(32, 16, 16, 2)
+EIFP_PLAN(32, 8, 8, 4)
+EIFP_PLAN(48, 12, 12, 4)
+EIFP_PLAN(48, 6, 6, 2, 2, 2)
+EIFP_PLAN(64, 16, 16, 4)
+EIFP_PLAN(64, 8, 8, 8)
+EIFP_PLAN(96, 12, 12, 4, 2)
+EIFP_PLAN(96, 6, 6, 2, 2, 2, 2)
+EIFP_PLAN(128, 16, 16, 8)
+EIFP_PLAN(128, 8, 8, 8, 2)
+EIFP_PLAN(192, 12, 12, 4, 4)
+EIFP_PLAN(256, 16, 16, 16)
+EIFP_PLAN(256, 8, 8, 8, 4)
+EIFP_PLAN(384, 12, 12, 4, 4, 2)
+EIFP_PLAN(512, 16, 16, 16, 2)
+EIFP_PLAN(512, 8, 8, 8, 8)
+// four and six values per thread (low register pressure, for the six-component z pass in FP64)
+EIFP_PLAN(8, 4, 4, 2)
+EIFP_PLAN(32, 4, 4, 4, 2)
+EIFP_PLAN(64, 4, 4, 4, 4)
+EIFP_PLAN(128, 4, 4, 4, 4, 2)
+EIFP_PLAN(256, 4, 4, 4, 4, 4)
+EIFP_PLAN(512, 4, 4, 4, 4, 4, 2)
+EIFP_PLAN(192, 6, 6, 2, 2, 2, 2, 2)
+EIFP_PLAN(384, 6, 6, 2, 2, 2, 2, 2, 2)
+#undef EIFP_PLAN
+
+template <class P, int s>
+__host__ __device__ constexpr int span_before() {  // product of the radices of stages < s
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= P::R[i];
+    return p;
+}
+
+// Register index idx of the first stage (idx = u R0 + r) owns position t + T*m0(idx);
+// after the last stage, idx = u RL + r owns position t + T*mL(idx).
+template <class P>
+__host__ __device__ constexpr int m_first(int idx) {
+    return idx / P::R[0] + (idx % P::R[0]) * (P::E / P::R[0]);
+}
+template <class P>
+__host__ __device__ constexpr int m_last(int idx) {
+    return idx / P::R[P::S - 1] + (idx % P::R[P::S - 1]) * (P::E / P::R[P::S - 1]);
+}
+
+// Runs stages s..S-1.  v holds stage-s inputs: v[u R + r] = x[j + r N/R], j = t + T u.
+// tw[k * TWS] = exp(-2 pi i k / N) for k < N (forward table; conj for the inverse).
+// Lds provides st(pos, v), ld(pos) for this thread's pencil and sync().
+template <class P, int s, bool INV, int TWS, typename T, class Lds>
+__device__ __forceinline__ void fft_stages(cpx<T> (&v)[P::E], int t, Lds& lds, const cpx<T>* __restrict__ tw) {
+    constexpr int N = P::N, E = P::E, TT = P::T;
+    constexpr int R = P::R[s];
+    constexpr int NS = span_before<P, s>();
+    constexpr int NB = E / R;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int j = t + TT * u;
+        if constexpr (NS > 1) {
+            const int jm = j % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const cpx<T> w = tw[(jm * r * (N / (NS * R))) * TWS];
+                v[u * R + r] = INV ? cmulc(v[u * R + r], w) : cmul(v[u * R + r], w);
+            }
+        }
+        Dft<R, INV, T>::run(&v[u * R]);
+    }
+    if constexpr (s + 1 < P::S) {
+        constexpr int R2 = P::R[s + 1];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = t + TT * u;
+            const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds.st(base + r * NS, v[u * R + r]);
+        }
+        lds.sync();
+#pragma unroll
+        for (int u = 0; u < E / R2; ++u) {
+            const int j = t + TT * u;
+#pragma unroll
+            for (int r = 0; r < R2; ++r) v[u * R2 + r] = lds.ld(j + r * (N / R2));
+        }
+        lds.sync();
+        fft_stages<P, s + 1, INV, TWS>(v, t, lds, tw);
+    }
+}
+
+// After a forward transform the registers are in last-stage order; an inverse
+// transform expects first-stage order.  Permute in registers (compile-time indices).
+template <class P>
+__host__ __device__ constexpr int last_slot_of_first(int idx) {
+    // the idx' with m_last(idx') == m_first(idx)
+    int found = 0;
+    for (int k = 0; k < P::E; ++k)
+        if (m_last<P>(k) == m_first<P>(idx)) found = k;
+    return found;
+}
+
+template <class P, typename T>
+__device__ __forceinline__ void last_to_first(cpx<T> (&v)[P::E]) {
+    cpx<T> w[P::E];
+#pragma unroll
+    for (int i = 0; i < P::E; ++i) w[i] = v[last_slot_of_first<P>(i)];
+#pragma unroll
+    for (int i = 0; i < P::E; ++i) v[i] = w[i];
+}
+
+template <class P, bool INV, int TWS, typename T, class Lds>
+__device__ __forceinline__ void fft_pencil(cpx<T> (&v)[P::E], int t, Lds& lds, const cpx<T>* __restrict__ tw) {
+    fft_stages<P, 0, INV, TWS>(v, t, lds, tw);
+}
+
+// LDS views.  Columns: a tile of B pencils stored [pos][col] (real and imaginary parts
+// in separate planes), so the B lanes of one position hit consecutive banks.
+template <typename T, int B>
+struct LdsCols {
+    T* re;
+    T* im;
+    int c;
+    __device__ __forceinline__ void st(int pos, cpx<T> a) { re[pos * B + c] = a.x; im[pos * B + c] = a.y; }
+    __device__ __forceinline__ cpx<T> ld(int pos) const { return {re[pos * B + c], im[pos * B + c]}; }
+    __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+
+// Rows: P pencils stored one after another with pitch LD.
+template <typename T, int LD>
+struct LdsRows {
+    T* re;
+    T* im;
+    int p;
+    __device__ __forceinline__ void st(int pos, cpx<T> a) { re[p * LD + pos] = a.x; im[p * LD + pos] = a.y; }
+    __device__ __forceinline__ cpx<T> ld(int pos) const { return {re[p * LD + pos], im[p * LD + pos]}; }
+    __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+
+}  // namespace eifp

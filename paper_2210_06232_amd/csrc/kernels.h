@@ -1,0 +1,385 @@
+// kernels.h -- the five passes of one EI-FP time step and their helpers.
+//
+// State layout in HBM: six real components (Hx, Hy, Hz, Ex, Ey, Ez), each
+// [Nz][Ny][Nx] with x fastest (the vector ordering of Sec. 2.2).  The transforms run
+// in place on the same bytes viewed as [6][Nz][Ny][M] complex, M = Nx/2:
+//
+//   x pass   each row of Nx reals is a length-M complex FFT followed by the real-to-
+//            complex split; the row then holds X[1..M-1] and, in slot 0, the packed pair
+//            X[0] + i X[M].  The paper sets the Nyquist wavenumber to zero (Sec. 2.3),
+//            so the kx = 0 and kx = Nx/2 planes see the same propagator; the packed
+//            column is therefore propagated and transformed along y and z as one
+//            complex column with no unpacking.
+//   y pass   C2C along y on tiles of B adjacent columns (coalesced along x).
+//   z pass   fused: C2C along z for all six components of a tile, the mode-wise
+//            exponential propagator (Prop. 2.1/2.2, Alg. 2 step 4) with the 1/(Nx Ny Nz)
+//            of the inverse transform folded in, the invariant partial sums, and the
+//            inverse C2C along z.
+//   y^-1, x^-1 as above in reverse (complex-to-real split back).
+#pragma once
+#include "fft_core.h"
+
+namespace eifp {
+
+// Per-step scalars for the z pass (formed in FP64 on the host).
+struct PropParams {
+    double tau_s;      // tau / sqrt(mu eps)
+    double rh;         // sqrt(mu / eps): weight of i k x H^ in E^'
+    double re;         // sqrt(eps / mu): weight of i k x E^ in H^'
+    double inv_ns;     // 1 / (Nx Ny Nz)
+    double nu[3];      // 2 pi / L_w
+    double mu, eps;
+};
+
+// invariant partial sums per workgroup (all in FP64)
+enum { INV_E1 = 0, INV_H1, INV_M1X, INV_M1Y, INV_M1Z, INV_DIVH, INV_DIVE, INV_NPART = 8 };
+
+// Omega_w[m] of Sec. 2.3: nu m for m < n/2, 0 at the Nyquist index, nu (m - n) above.
+__device__ __forceinline__ double omega(int m, int n, double nu) {
+    const int half = n >> 1;
+    return m < half ? nu * (double)m : (m == half ? 0.0 : nu * (double)(m - n));
+}
+
+// ---------------------------------------------------------------------------------
+// x pass: real <-> packed half spectrum along contiguous rows
+// ---------------------------------------------------------------------------------
+// twx[k] = exp(-2 pi i k / Nx), k < Nx (the length-M FFT reads every second entry).
+template <typename T, class P, int NP>
+__global__ void __launch_bounds__(P::T * NP)
+k_x_fwd(const cpx<T>* src, cpx<T>* dst, long nrows, const cpx<T>* __restrict__ twx) {
+    constexpr int M = P::N, E = P::E, TT = P::T, LD = M + 1;
+    __shared__ T s_re[NP * LD];
+    __shared__ T s_im[NP * LD];
+    const int t = threadIdx.x % TT, p = threadIdx.x / TT;
+    const long row = (long)blockIdx.x * NP + p;
+    const bool active = row < nrows;
+    const cpx<T>* in = src + row * M;
+    cpx<T> v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = active ? in[t + TT * m_first<P>(i)] : cpx<T>{0, 0};
+    LdsRows<T, LD> lds{s_re, s_im, p};
+    fft_pencil<P, false, 2>(v, t, lds, twx);
+    // split: X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W^k (Z[k] - conj Z[M-k]),  W = exp(-2 pi i/Nx)
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E; ++i) lds.st(t + TT * m_last<P>(i), v[i]);
+    __syncthreads();
+    cpx<T>* out = dst + row * M;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int k = t + TT * m_last<P>(i);
+        const cpx<T> z = v[i];
+        cpx<T> r;
+        if (k == 0) {
+            r = {z.x + z.y, z.x - z.y};  // X[0] + i X[M]
+        } else {
+            const cpx<T> zc = conj(lds.ld(M - k));
+            const cpx<T> ev = scale(z + zc, (T)0.5);
+            const cpx<T> od = scale(mulmi(z - zc), (T)0.5);  // (Z - conj Z')/(2i)
+            r = ev + cmul(twx[k], od);
+        }
+        if (active) out[k] = r;
+    }
+}
+
+template <typename T, class P, int NP>
+__global__ void __launch_bounds__(P::T * NP)
+k_x_inv(const cpx<T>* src, cpx<T>* dst, long nrows, const cpx<T>* __restrict__ twx) {
+    constexpr int M = P::N, E = P::E, TT = P::T, LD = M + 1;
+    __shared__ T s_re[NP * LD];
+    __shared__ T s_im[NP * LD];
+    const int t = threadIdx.x % TT, p = threadIdx.x / TT;
+    const long row = (long)blockIdx.x * NP + p;
+    const bool active = row < nrows;
+    const cpx<T>* in = src + row * M;
+    LdsRows<T, LD> lds{s_re, s_im, p};
+    cpx<T> v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = active ? in[t + TT * m_first<P>(i)] : cpx<T>{0, 0};
+#pragma unroll
+    for (int i = 0; i < E; ++i) lds.st(t + TT * m_first<P>(i), v[i]);
+    __syncthreads();
+    // merge: Z[k] = (X[k] + conj X[M-k]) + i W^-k (X[k] - conj X[M-k]); Z[0] from X[0], X[M]
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int k = t + TT * m_first<P>(i);
+        const cpx<T> x = v[i];
+        if (k == 0) {
+            v[i] = {x.x + x.y, x.x - x.y};
+        } else {
+            const cpx<T> xc = conj(lds.ld(M - k));
+            v[i] = (x + xc) + muli(cmulc(x - xc, twx[k]));
+        }
+    }
+    __syncthreads();
+    fft_pencil<P, true, 2>(v, t, lds, twx);
+    cpx<T>* out = dst + row * M;
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) out[t + TT * m_last<P>(i)] = v[i];
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// y pass: C2C along y, tiles of B adjacent x columns, one component per workgroup
+// ---------------------------------------------------------------------------------
+template <typename T, class P, int B, bool INV>
+__global__ void __launch_bounds__(P::T * B)
+k_y(cpx<T>* __restrict__ buf, int M, int nz, const cpx<T>* __restrict__ twy) {
+    constexpr int NY = P::N, E = P::E, TT = P::T;
+    __shared__ T s_re[NY * B];
+    __shared__ T s_im[NY * B];
+    const int c = threadIdx.x % B, t = threadIdx.x / B;
+    const int col = blockIdx.x * B + c;
+    const int z = blockIdx.y;
+    const int comp = blockIdx.z;
+    const bool active = col < M;
+    cpx<T>* base = buf + ((long)comp * nz + z) * (long)NY * M + col;
+    cpx<T> v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = active ? base[(long)(t + TT * m_first<P>(i)) * M] : cpx<T>{0, 0};
+    LdsCols<T, B> lds{s_re, s_im, c};
+    fft_pencil<P, INV, 1>(v, t, lds, twy);
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) base[(long)(t + TT * m_last<P>(i)) * M] = v[i];
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// z pass: forward z, propagate, invariant partials, inverse z (all six components)
+// ---------------------------------------------------------------------------------
+enum ZMode { Z_STEP = 0, Z_FORWARD = 1 };
+
+template <typename T, class P>
+__device__ __forceinline__ void load_col(cpx<T> (&v)[P::E], const cpx<T>* base, long stride, int t, bool active) {
+#pragma unroll
+    for (int i = 0; i < P::E; ++i) v[i] = active ? base[(long)(t + P::T * m_first<P>(i)) * stride] : cpx<T>{0, 0};
+}
+
+template <typename T, class P>
+__device__ __forceinline__ void store_col(const cpx<T> (&v)[P::E], cpx<T>* base, long stride, int t, bool active) {
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < P::E; ++i) base[(long)(t + P::T * m_last<P>(i)) * stride] = v[i];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ double dreal(T a) { return (double)a; }
+
+// Accumulate the weighted spectral sums of one mode.  h, e are the six propagated
+// coefficients already multiplied by 1/N_S, so sums of their products are the
+// discrete inner products of Sec. 4 (Parseval) with no further scaling.
+template <typename T>
+__device__ __forceinline__ void accumulate_invariants(double (&acc)[INV_NPART], double w, double bx, double by, double bz,
+                                                      const cpx<T>* h, const cpx<T>* e, double mu, double eps) {
+    const double hr[3] = {dreal(h[0].x), dreal(h[1].x), dreal(h[2].x)};
+    const double hi[3] = {dreal(h[0].y), dreal(h[1].y), dreal(h[2].y)};
+    const double er[3] = {dreal(e[0].x), dreal(e[1].x), dreal(e[2].x)};
+    const double ei[3] = {dreal(e[0].y), dreal(e[1].y), dreal(e[2].y)};
+    double h2 = 0, e2 = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        h2 += hr[c] * hr[c] + hi[c] * hi[c];
+        e2 += er[c] * er[c] + ei[c] * ei[c];
+    }
+    acc[INV_E1] += w * 0.5 * (mu * h2 + eps * e2);
+    // b . (Re U x Im U)
+    const double hc = bx * (hr[1] * hi[2] - hr[2] * hi[1]) + by * (hr[2] * hi[0] - hr[0] * hi[2]) +
+                      bz * (hr[0] * hi[1] - hr[1] * hi[0]);
+    const double ec = bx * (er[1] * ei[2] - er[2] * ei[1]) + by * (er[2] * ei[0] - er[0] * ei[2]) +
+                      bz * (er[0] * ei[1] - er[1] * ei[0]);
+    acc[INV_H1] += w * (hc / eps + ec / mu);
+    // Im H . Re E - Re H . Im E
+    double q = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q += hi[c] * er[c] - hr[c] * ei[c];
+    acc[INV_M1X] += w * bx * q;
+    acc[INV_M1Y] += w * by * q;
+    acc[INV_M1Z] += w * bz * q;
+    const double dhr = bx * hr[0] + by * hr[1] + bz * hr[2], dhi = bx * hi[0] + by * hi[1] + bz * hi[2];
+    const double der = bx * er[0] + by * er[1] + bz * er[2], dei = bx * ei[0] + by * ei[1] + bz * ei[2];
+    acc[INV_DIVH] += w * mu * mu * (dhr * dhr + dhi * dhi);
+    acc[INV_DIVE] += w * eps * eps * (der * der + dei * dei);
+}
+
+// Block-wide sum of INV_NPART doubles in a fixed order; thread 0 writes the partials.
+template <int NT>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[INV_NPART], double* __restrict__ out, double* s_red) {
+#pragma unroll
+    for (int q = 0; q < INV_NPART; ++q) {
+        double a = acc[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+        acc[q] = a;
+    }
+    constexpr int NW = (NT + 63) / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < INV_NPART; ++q) s_red[wid * INV_NPART + q] = acc[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < INV_NPART) {
+        double a = 0;
+        for (int w = 0; w < NW; ++w) a += s_red[w * INV_NPART + threadIdx.x];
+        out[threadIdx.x] = a;
+    }
+}
+
+// Propagate one mode in place.  b = (Omega_x, Omega_y, Omega_z).  With k = b/|b|,
+// theta = tau |b| / sqrt(mu eps), L(U) = k (k.U), X(U) = i k x U:
+//   H' = L(H) + cos(theta) (H - L(H)) - sin(theta) sqrt(eps/mu) X(E)
+//   E' = L(E) + cos(theta) (E - L(E)) + sin(theta) sqrt(mu/eps) X(H)
+// which is the c/s matrix of Prop. 2.2 applied as in Alg. 2 step 4 (c = k k^T +
+// cos(theta) (I - k k^T), s_12 = i sin(theta) k_z, ...).  |b| = 0 keeps the mode.
+// All coefficients are formed in FP64 and rounded to T; everything is scaled by 1/N_S.
+template <typename T>
+__device__ __forceinline__ void propagate_mode(cpx<T>* h, cpx<T>* e, double bx, double by, double bz, const PropParams& pp) {
+    const double b2 = bx * bx + by * by + bz * bz;
+    if (b2 == 0.0) {
+        const T s = (T)pp.inv_ns;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            h[c] = scale(h[c], s);
+            e[c] = scale(e[c], s);
+        }
+        return;
+    }
+    const double bn = sqrt(b2);
+    const double ib = 1.0 / bn;
+    double sn, cs;
+    sincos(pp.tau_s * bn, &sn, &cs);
+    const T kx = (T)(bx * ib), ky = (T)(by * ib), kz = (T)(bz * ib);
+    const T cT = (T)(cs * pp.inv_ns);                 // transverse part
+    const T dL = (T)((1.0 - cs) * pp.inv_ns);         // longitudinal minus transverse
+    const T sE = (T)(sn * pp.re * pp.inv_ns);
+    const T sH = (T)(sn * pp.rh * pp.inv_ns);
+    const cpx<T> kh = {kx * h[0].x + ky * h[1].x + kz * h[2].x, kx * h[0].y + ky * h[1].y + kz * h[2].y};
+    const cpx<T> ke = {kx * e[0].x + ky * e[1].x + kz * e[2].x, kx * e[0].y + ky * e[1].y + kz * e[2].y};
+    // k x U
+    const cpx<T> xe[3] = {{ky * e[2].x - kz * e[1].x, ky * e[2].y - kz * e[1].y},
+                          {kz * e[0].x - kx * e[2].x, kz * e[0].y - kx * e[2].y},
+                          {kx * e[1].x - ky * e[0].x, kx * e[1].y - ky * e[0].y}};
+    const cpx<T> xh[3] = {{ky * h[2].x - kz * h[1].x, ky * h[2].y - kz * h[1].y},
+                          {kz * h[0].x - kx * h[2].x, kz * h[0].y - kx * h[2].y},
+                          {kx * h[1].x - ky * h[0].x, kx * h[1].y - ky * h[0].y}};
+    const T kk[3] = {kx, ky, kz};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        // i (k x E) = (-Im, Re)
+        const cpx<T> hn = {cT * h[c].x + dL * kk[c] * kh.x + sE * xe[c].y, cT * h[c].y + dL * kk[c] * kh.y - sE * xe[c].x};
+        const cpx<T> en = {cT * e[c].x + dL * kk[c] * ke.x - sH * xh[c].y, cT * e[c].y + dL * kk[c] * ke.y + sH * xh[c].x};
+        h[c] = hn;
+        e[c] = en;
+    }
+}
+
+template <typename T, class P, int B, int MODE>
+__global__ void __launch_bounds__(P::T * B)
+k_z(cpx<T>* __restrict__ buf, int M, int ny, long comp_stride, const cpx<T>* __restrict__ twz, PropParams pp,
+    double* __restrict__ partials, int want_inv) {
+    constexpr int NZ = P::N, E = P::E, TT = P::T;
+    __shared__ T s_re[NZ * B];
+    __shared__ T s_im[NZ * B];
+    __shared__ double s_red[((P::T * B + 63) / 64) * INV_NPART];
+    const int c = threadIdx.x % B, t = threadIdx.x / B;
+    const int col = blockIdx.x * B + c;
+    const int y = blockIdx.y;
+    const bool active = col < M;
+    const long zstride = (long)ny * M;
+    cpx<T>* base = buf + (long)y * M + col;
+    LdsCols<T, B> lds{s_re, s_im, c};
+
+    cpx<T> v[6][E];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) load_col<T, P>(v[q], base + q * comp_stride, zstride, t, active);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) fft_pencil<P, false, 1>(v[q], t, lds, twz);
+
+    const double bx = col == 0 ? 0.0 : pp.nu[0] * (double)col;  // packed column: Omega_x = 0 at 0 and Nx/2
+    const double by = omega(y, ny, pp.nu[1]);
+    double acc[INV_NPART];
+#pragma unroll
+    for (int q = 0; q < INV_NPART; ++q) acc[q] = 0.0;
+    const double w = col == 0 ? 1.0 : 2.0;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int kz = t + TT * m_last<P>(i);
+        const double bz = omega(kz, NZ, pp.nu[2]);
+        cpx<T> h[3] = {v[0][i], v[1][i], v[2][i]};
+        cpx<T> e[3] = {v[3][i], v[4][i], v[5][i]};
+        if (MODE == Z_STEP) {
+            propagate_mode(h, e, bx, by, bz, pp);
+        } else {
+            const T s = (T)pp.inv_ns;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                h[q] = scale(h[q], s);
+                e[q] = scale(e[q], s);
+            }
+        }
+        if (want_inv && active) accumulate_invariants(acc, w, bx, by, bz, h, e, pp.mu, pp.eps);
+        if (MODE == Z_STEP) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                v[q][i] = h[q];
+                v[3 + q][i] = e[q];
+            }
+        }
+    }
+    if (want_inv) {
+        const int nbx = gridDim.x;
+        block_reduce_store<P::T * B>(acc, partials + ((long)blockIdx.y * nbx + blockIdx.x) * INV_NPART, s_red);
+    }
+    if (MODE == Z_STEP) {
+        // z^-1 then store; Z_FORWARD leaves the (scaled) spectrum untouched in memory
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            last_to_first<P>(v[q]);
+            fft_pencil<P, true, 1>(v[q], t, lds, twz);
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) store_col<T, P>(v[q], base + q * comp_stride, zstride, t, active);
+    }
+}
+
+// Forward-only variant that stores the (unscaled) spectrum, for diagnostics.
+template <typename T, class P, int B>
+__global__ void __launch_bounds__(P::T * B)
+k_z_fwd_store(cpx<T>* __restrict__ buf, int M, int ny, long comp_stride, const cpx<T>* __restrict__ twz) {
+    constexpr int NZ = P::N, E = P::E;
+    __shared__ T s_re[NZ * B];
+    __shared__ T s_im[NZ * B];
+    const int c = threadIdx.x % B, t = threadIdx.x / B;
+    const int col = blockIdx.x * B + c;
+    const int y = blockIdx.y;
+    const bool active = col < M;
+    const long zstride = (long)ny * M;
+    LdsCols<T, B> lds{s_re, s_im, c};
+    const int comp = blockIdx.z;
+    cpx<T>* base = buf + comp * comp_stride + (long)y * M + col;
+    cpx<T> v[E];
+    load_col<T, P>(v, base, zstride, t, active);
+    fft_pencil<P, false, 1>(v, t, lds, twz);
+    store_col<T, P>(v, base, zstride, t, active);
+}
+
+// ---------------------------------------------------------------------------------
+// deterministic compensated finalize of the invariant partials
+// ---------------------------------------------------------------------------------
+// out: [0] E1 [1] H1 [2..4] M1 [5] ||div~(mu H)||_N [6] ||div~(eps E)||_N
+__global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ partials, int nparts, double* __restrict__ out);
+
+// FP64 <-> T conversion for upload / download of the state.
+template <typename TO, typename TI>
+__global__ void __launch_bounds__(256) k_convert(const TI* __restrict__ in, TO* __restrict__ out, long n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long q = i; q < n; q += stride) out[q] = (TO)in[q];
+}
+
+}  // namespace eifp

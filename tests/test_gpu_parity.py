@@ -1,0 +1,224 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle, element by
+element on the same seeded inputs, plus exact solutions at the benchmark's full sizes.
+
+Tolerances: FP64 1e-12 relative (energy norm of Thm 3.4); FP32 2e-6 relative L2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2210_06232_amd import inputs
+from tests.helpers import energy_rel_error
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 2e-6
+
+# shapes (nx, ny, nz): radix 2/4/8/16 and 3/6/12 plans, several tiles with ragged tails
+SHAPES = [
+    (4, 4, 4), (8, 8, 8), (6, 12, 8), (16, 24, 12), (24, 16, 32), (12, 48, 6),
+    (32, 32, 32), (64, 8, 16), (192, 8, 8), (8, 96, 4), (4, 6, 192), (128, 4, 8),
+    (48, 64, 96), (256, 4, 4), (4, 256, 8), (8, 4, 256), (384, 4, 4), (4, 384, 4), (4, 4, 384),
+    (512, 4, 4), (4, 512, 4), (4, 4, 512),
+]
+DOMAIN = (0.0, 2 * math.pi, -1.0, 4 * math.pi - 1.0, 0.5, 2.5)
+
+
+def eifp():
+    from paper_2210_06232_amd import eifp as m
+    m.load()
+    return m
+
+
+def packed_expected(H, E):
+    """Oracle 3-D DFT of the six components, in the kernels' packed half-spectrum form."""
+    comps = np.concatenate([H, E])
+    nx = comps.shape[-1]
+    m = nx // 2
+    out = []
+    for c in comps:
+        F = orc.fft3(c.astype(complex), -1)
+        P = F[:, :, :m].copy()
+        P[:, :, 0] = F[:, :, 0] + 1j * F[:, :, m]
+        out.append(P)
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_forward_transform_matches_oracle(shape, prec):
+    m = eifp()
+    H, E = inputs.white_noise_fields(shape, seed=sum(shape))
+    with m.Solver(H, E, DOMAIN, 1.0, 1.0, prec) as s:
+        got = s.spectrum()
+        H2, E2 = s.fields()
+    want = packed_expected(H, E)
+    scale = np.max(np.abs(want))
+    tol = 1e-14 * math.log2(max(shape)) * 4 if prec == "fp64" else 2e-7 * math.log2(max(shape)) * 4
+    assert np.max(np.abs(got - want)) <= tol * scale
+    # the diagnostic leaves the state untouched
+    if prec == "fp64":
+        np.testing.assert_array_equal(H2, H)
+        np.testing.assert_array_equal(E2, E)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fp64_steps_match_oracle(shape):
+    m = eifp()
+    H, E = inputs.white_noise_fields(shape, seed=1 + sum(shape))   # full spectrum incl. Nyquist
+    mu, eps, tau, n = 1.3, 0.7, 0.37, 3
+    Ho, Eo, _ = orc.step(H, E, DOMAIN, mu, eps, tau, n)
+    with m.Solver(H, E, DOMAIN, mu, eps, "fp64") as s:
+        s.step(tau, n)
+        Hg, Eg = s.fields()
+    assert energy_rel_error(Hg, Eg, Ho, Eo, mu, eps) <= FP64_TOL
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (12, 16, 24), (32, 32, 32), (192, 8, 8), (4, 4, 384)])
+def test_fp32_one_step_local_error(shape):
+    m = eifp()
+    H = inputs.random_divfree(shape, DOMAIN, 7, p=1.0)
+    E = inputs.random_divfree(shape, DOMAIN, 8, p=1.0)
+    mu, eps, tau = 1.0, 2.0, 0.1
+    Ho, Eo, _ = orc.step(H, E, DOMAIN, mu, eps, tau, 1)
+    with m.Solver(H, E, DOMAIN, mu, eps, "fp32") as s:
+        s.step(tau, 1)
+        Hg, Eg = s.fields()
+    assert energy_rel_error(Hg, Eg, Ho, Eo, mu, eps) <= FP32_TOL
+
+
+@pytest.mark.parametrize("mu,eps,t0", [(1.0, 1.0, 0.0), (1.0, 1.0, 0.3), (1.0, 2.0, 0.3)])
+def test_standing_wave_16cubed(mu, eps, t0):
+    # the 16^3 standing-wave workload: tau = 0.01, 100 steps
+    m = eifp()
+    H0, E0, dom = inputs.standing_wave(16, 0.0, mu, eps, t0)
+    Hx, Ex, _ = inputs.standing_wave(16, 1.0, mu, eps, t0)
+    Ho, Eo, _ = orc.step(H0, E0, dom, mu, eps, 0.01, 100)
+    with m.Solver(H0, E0, dom, mu, eps, "fp64") as s:
+        inv0 = s.invariants()
+        s.step(0.01, 100)
+        Hg, Eg = s.fields()
+        inv1 = s.invariants()
+    assert energy_rel_error(Hg, Eg, Ho, Eo, mu, eps) <= FP64_TOL
+    assert energy_rel_error(Hg, Eg, Hx, Ex, mu, eps) <= FP64_TOL
+    assert abs(inv1["energy"] - inv0["energy"]) <= 1e-13 * inv0["energy"]
+    assert inv1["steps_done"] == 100 and abs(inv1["t"] - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("kind", ["divfree", "white"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_invariants_match_oracle(kind, prec):
+    m = eifp()
+    shape = (12, 8, 16)
+    mu, eps = 1.3, 0.7
+    if kind == "divfree":
+        H = inputs.random_divfree(shape, DOMAIN, 3, p=1.0)
+        E = inputs.random_divfree(shape, DOMAIN, 4, p=1.0)
+    else:
+        H, E = inputs.white_noise_fields(shape, 5)
+    tau, n = 0.25, 4
+    Ho, Eo, _ = orc.step(H, E, DOMAIN, mu, eps, tau, n)
+    want0 = orc.invariants(H, E, DOMAIN, mu, eps)
+    want1 = orc.invariants(Ho, Eo, DOMAIN, mu, eps)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    with m.Solver(H, E, DOMAIN, mu, eps, prec) as s:
+        got0 = s.invariants()        # before any step: forward-only evaluation
+        s.step(tau, n)
+        got1 = s.invariants()        # reduced inside the last step
+    e_ref = math.sqrt(want0["E1"] * want0["E2"])
+    for got, want in ((got0, want0), (got1, want1)):
+        assert abs(got["energy"] - want["E1"]) <= tol * want["E1"]
+        assert abs(got["helicity"] - want["H1"]) <= tol * e_ref
+        for k, c in enumerate("xyz"):
+            assert abs(got["momentum"][k] - want[f"M1_{c}"]) <= tol * e_ref
+        dscale = max(1.0, want["divH_l2"], want["divE_l2"])
+        assert abs(got["div_h_l2"] - want["divH_l2"]) <= tol * dscale * 10
+        assert abs(got["div_e_l2"] - want["divE_l2"]) <= tol * dscale * 10
+
+
+def test_invariants_bitwise_deterministic():
+    m = eifp()
+    H, E = inputs.random_fields((32, 32, 32), inputs.CUBE_2PI, workload=1)
+    runs = []
+    for _ in range(2):
+        with m.Solver(H, E, inputs.CUBE_2PI, 1.0, 2.0, "fp64") as s:
+            s.step(0.05, 5)
+            runs.append((s.invariants(), s.fields()))
+    assert runs[0][0] == runs[1][0]
+    np.testing.assert_array_equal(runs[0][1][0], runs[1][1][0])
+
+
+def _plane_wave_sum(shape, dom, t, mu, eps, modes):
+    H = np.zeros((3,) + shape[::-1])
+    E = np.zeros_like(H)
+    for mvec, e, ph in modes:
+        h, ee = inputs.plane_wave(shape, dom, mvec, e, t, mu, eps, phase=ph)
+        H += h
+        E += ee
+    return H, E
+
+
+def _modes(dom, rng, count, mmax):
+    L = np.array([dom[1] - dom[0], dom[3] - dom[2], dom[5] - dom[4]])
+    out = []
+    for _ in range(count):
+        mvec = rng.integers(-mmax, mmax + 1, size=3)
+        if not mvec.any():
+            mvec[0] = 1
+        k = 2 * math.pi * mvec / L
+        e = np.cross(k, rng.standard_normal(3))
+        out.append((mvec, e / np.linalg.norm(e), rng.uniform(0, 2 * math.pi)))
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", 2e-5)])
+def test_full_size_256_exact_plane_waves(prec, tol):
+    # 256^3 on [0,2pi] x [0,4pi] x [0,2pi], the benchmark's launch configuration: a sum of
+    # plane waves is evolved exactly by the scheme, so the exact solution is the
+    # reference at every point (checked at all points and at 64 sampled ones).
+    m = eifp()
+    shape = (256, 256, 256)
+    dom = (0.0, 2 * math.pi, 0.0, 4 * math.pi, 0.0, 2 * math.pi)
+    mu, eps, tau, n = 1.0, 1.0, 0.1, 10
+    modes = _modes(dom, np.random.default_rng(256), 6, 40)
+    H0, E0 = _plane_wave_sum(shape, dom, 0.0, mu, eps, modes)
+    Hx, Ex = _plane_wave_sum(shape, dom, tau * n, mu, eps, modes)
+    with m.Solver(H0, E0, dom, mu, eps, prec) as s:
+        s.step(tau, n)
+        Hg, Eg = s.fields()
+    assert energy_rel_error(Hg, Eg, Hx, Ex, mu, eps) <= tol
+    rng = np.random.default_rng(1)
+    idx = tuple(rng.integers(0, 256, size=(3, 64)))
+    scale = np.max(np.abs(Hx))
+    for c in range(3):
+        assert np.max(np.abs(Hg[c][idx] - Hx[c][idx])) <= 10 * tol * scale
+
+
+def test_full_size_128_one_step_vs_oracle():
+    # 128^3 random divergence-free fields (mu = 1, eps = 2, tau = 0.05): one step against
+    # the oracle over the whole grid.
+    m = eifp()
+    shape = (128, 128, 128)
+    H, E = inputs.random_fields(shape, inputs.CUBE_2PI, workload=1, p=2.0)
+    Ho, Eo, _ = orc.step(H, E, inputs.CUBE_2PI, 1.0, 2.0, 0.05, 1)
+    with m.Solver(H, E, inputs.CUBE_2PI, 1.0, 2.0, "fp64") as s:
+        s.step(0.05, 1)
+        Hg, Eg = s.fields()
+    assert energy_rel_error(Hg, Eg, Ho, Eo, 1.0, 2.0) <= FP64_TOL
+
+
+def test_device_error_paths():
+    m = eifp()
+    H, E = inputs.white_noise_fields((8, 8, 8), 0)
+    with m.Solver(H, E, inputs.CUBE_2PI) as s:
+        with pytest.raises(m.EifpError) as ei:
+            s.step(float("nan"), 1)
+        assert ei.value.status == m.EIFP_ERR_INVALID_ARG
+        with pytest.raises(m.EifpError):
+            s.step(0.1, -1)
+        s.step(0.1, 0)
+        assert s.invariants()["steps_done"] == 0
+        assert s.device_bytes() > 6 * 8 ** 3 * 8
