@@ -256,7 +256,7 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[P::E], int t, Lds& lds, c
 #pragma unroll
             for (int r = 0; r < R2; ++r) v[u * R2 + r] = lds.ld(j + r * (N / R2));
         }
-        lds.sync();
+        lds.after_load();
         fft_stages<P, s + 1, INV, TWS>(v, t, lds, tw);
     }
 }
@@ -288,14 +288,42 @@ __device__ __forceinline__ void fft_pencil(cpx<T> (&v)[P::E], int t, Lds& lds, c
 
 // LDS views.  Columns: a tile of B pencils stored [pos][col] (real and imaginary parts
 // in separate planes), so the B lanes of one position hit consecutive banks.
+// Rows of the [pos][col] views have a pitch of B + 1 elements: positions that differ by
+// a power of two then fall in different LDS banks (a pitch of B would put the lanes of a
+// wave that share a column on the same banks).
+// after_load(): a single buffer needs a second barrier before it is written again; the
+// double-buffered views flip to the other buffer instead, which is safe because the
+// next write to this buffer comes after the next exchange's barrier.
 template <typename T, int B>
 struct LdsCols {
     T* re;
     T* im;
     int c;
-    __device__ __forceinline__ void st(int pos, cpx<T> a) { re[pos * B + c] = a.x; im[pos * B + c] = a.y; }
-    __device__ __forceinline__ cpx<T> ld(int pos) const { return {re[pos * B + c], im[pos * B + c]}; }
+    __device__ __forceinline__ void st(int pos, cpx<T> a) { re[pos * (B + 1) + c] = a.x; im[pos * (B + 1) + c] = a.y; }
+    __device__ __forceinline__ cpx<T> ld(int pos) const { return {re[pos * (B + 1) + c], im[pos * (B + 1) + c]}; }
     __device__ __forceinline__ void sync() { __syncthreads(); }
+    __device__ __forceinline__ void after_load() { __syncthreads(); }
+};
+
+// Two alternating [pos][col] buffers of PLANE reals per plane (re, im): one barrier per
+// exchange.  base holds re0, im0, re1, im1.
+template <typename T, int B, int PLANE>
+struct LdsCols2 {
+    T* base;
+    int c;
+    int cur;
+    __device__ __forceinline__ T* re() const { return base + (2 * cur) * PLANE; }
+    __device__ __forceinline__ void st(int pos, cpx<T> a) {
+        T* r = re();
+        r[pos * (B + 1) + c] = a.x;
+        r[PLANE + pos * (B + 1) + c] = a.y;
+    }
+    __device__ __forceinline__ cpx<T> ld(int pos) const {
+        const T* r = re();
+        return {r[pos * (B + 1) + c], r[PLANE + pos * (B + 1) + c]};
+    }
+    __device__ __forceinline__ void sync() { __syncthreads(); }
+    __device__ __forceinline__ void after_load() { cur ^= 1; }
 };
 
 // Rows: P pencils stored one after another with pitch LD.
@@ -307,6 +335,43 @@ struct LdsRows {
     __device__ __forceinline__ void st(int pos, cpx<T> a) { re[p * LD + pos] = a.x; im[p * LD + pos] = a.y; }
     __device__ __forceinline__ cpx<T> ld(int pos) const { return {re[p * LD + pos], im[p * LD + pos]}; }
     __device__ __forceinline__ void sync() { __syncthreads(); }
+    __device__ __forceinline__ void after_load() { __syncthreads(); }
+};
+
+// Copy a twiddle table of n entries into LDS (all threads of the block take part).
+// The first FFT stage uses no twiddles and ends in a barrier, so no barrier is needed
+// between this copy and the first read.
+template <typename T>
+__device__ __forceinline__ void stage_table(cpx<T>* dst, const cpx<T>* __restrict__ src, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// Raw buffer access (gfx9 descriptor): one SGPR descriptor per array, a per-lane VGPR
+// byte offset and a wave-uniform SGPR byte offset.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T> struct BufIO;
+template <> struct BufIO<double> {
+    __device__ __forceinline__ static cpx<double> ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0);
+        return __builtin_bit_cast(cpx<double>, u);
+    }
+    __device__ __forceinline__ static void st(cpx<double> v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        using U4 = __attribute__((ext_vector_type(4))) unsigned int;
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v), r, (int)vo, (int)so, 0);
+    }
+};
+template <> struct BufIO<float> {
+    __device__ __forceinline__ static cpx<float> ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0);
+        return __builtin_bit_cast(cpx<float>, u);
+    }
+    __device__ __forceinline__ static void st(cpx<float> v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        using U2 = __attribute__((ext_vector_type(2))) unsigned int;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, (int)vo, (int)so, 0);
+    }
 };
 
 }  // namespace eifp

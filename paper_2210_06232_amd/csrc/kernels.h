@@ -29,6 +29,7 @@ struct PropParams {
     double inv_ns;     // 1 / (Nx Ny Nz)
     double nu[3];      // 2 pi / L_w
     double mu, eps;
+    double inv_mu, inv_eps;
 };
 
 // invariant partial sums per workgroup (all in FP64)
@@ -50,17 +51,20 @@ k_x_fwd(const cpx<T>* src, cpx<T>* dst, long nrows, const cpx<T>* __restrict__ t
     constexpr int M = P::N, E = P::E, TT = P::T, LD = M + 1;
     __shared__ T s_re[NP * LD];
     __shared__ T s_im[NP * LD];
+    __shared__ cpx<T> s_tw[2 * M];
+    stage_table(s_tw, twx, 2 * M);
     const int t = threadIdx.x % TT, p = threadIdx.x / TT;
     const long row = (long)blockIdx.x * NP + p;
     const bool active = row < nrows;
-    const cpx<T>* in = src + row * M;
+    // rows past the end read the last row (in bounds, never stored) instead of branching
+    const cpx<T>* in = src + (active ? row : nrows - 1) * M;
     cpx<T> v[E];
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = active ? in[t + TT * m_first<P>(i)] : cpx<T>{0, 0};
+    for (int i = 0; i < E; ++i) v[i] = in[t + TT * m_first<P>(i)];
     LdsRows<T, LD> lds{s_re, s_im, p};
-    fft_pencil<P, false, 2>(v, t, lds, twx);
+    if constexpr (P::S == 1) __syncthreads();  // twiddle table visible before the split
+    fft_pencil<P, false, 2>(v, t, lds, s_tw);
     // split: X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W^k (Z[k] - conj Z[M-k]),  W = exp(-2 pi i/Nx)
-    __syncthreads();
 #pragma unroll
     for (int i = 0; i < E; ++i) lds.st(t + TT * m_last<P>(i), v[i]);
     __syncthreads();
@@ -76,7 +80,7 @@ k_x_fwd(const cpx<T>* src, cpx<T>* dst, long nrows, const cpx<T>* __restrict__ t
             const cpx<T> zc = conj(lds.ld(M - k));
             const cpx<T> ev = scale(z + zc, (T)0.5);
             const cpx<T> od = scale(mulmi(z - zc), (T)0.5);  // (Z - conj Z')/(2i)
-            r = ev + cmul(twx[k], od);
+            r = ev + cmul(s_tw[k], od);
         }
         if (active) out[k] = r;
     }
@@ -88,14 +92,16 @@ k_x_inv(const cpx<T>* src, cpx<T>* dst, long nrows, const cpx<T>* __restrict__ t
     constexpr int M = P::N, E = P::E, TT = P::T, LD = M + 1;
     __shared__ T s_re[NP * LD];
     __shared__ T s_im[NP * LD];
+    __shared__ cpx<T> s_tw[2 * M];
+    stage_table(s_tw, twx, 2 * M);
     const int t = threadIdx.x % TT, p = threadIdx.x / TT;
     const long row = (long)blockIdx.x * NP + p;
     const bool active = row < nrows;
-    const cpx<T>* in = src + row * M;
+    const cpx<T>* in = src + (active ? row : nrows - 1) * M;
     LdsRows<T, LD> lds{s_re, s_im, p};
     cpx<T> v[E];
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = active ? in[t + TT * m_first<P>(i)] : cpx<T>{0, 0};
+    for (int i = 0; i < E; ++i) v[i] = in[t + TT * m_first<P>(i)];
 #pragma unroll
     for (int i = 0; i < E; ++i) lds.st(t + TT * m_first<P>(i), v[i]);
     __syncthreads();
@@ -108,11 +114,11 @@ k_x_inv(const cpx<T>* src, cpx<T>* dst, long nrows, const cpx<T>* __restrict__ t
             v[i] = {x.x + x.y, x.x - x.y};
         } else {
             const cpx<T> xc = conj(lds.ld(M - k));
-            v[i] = (x + xc) + muli(cmulc(x - xc, twx[k]));
+            v[i] = (x + xc) + muli(cmulc(x - xc, s_tw[k]));
         }
     }
     __syncthreads();
-    fft_pencil<P, true, 2>(v, t, lds, twx);
+    fft_pencil<P, true, 2>(v, t, lds, s_tw);
     cpx<T>* out = dst + row * M;
     if (active) {
 #pragma unroll
@@ -121,49 +127,58 @@ k_x_inv(const cpx<T>* src, cpx<T>* dst, long nrows, const cpx<T>* __restrict__ t
 }
 
 // ---------------------------------------------------------------------------------
-// y pass: C2C along y, tiles of B adjacent x columns, one component per workgroup
+// column access: tiles of B adjacent x columns, a pencil per column
+// ---------------------------------------------------------------------------------
+// Lane (c, t) of a tile owns column x0 + c and pencil positions t + T m.  Byte offsets
+// are 32-bit: the lane part goes in a VGPR, the position part m T stride (wave-uniform)
+// in the scalar offset of a raw buffer access.  Lanes past the last column load the
+// last column (in bounds, never stored) so that loads need no branch.
+template <typename T, class P>
+__device__ __forceinline__ void load_col(cpx<T> (&v)[P::E], __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned sstep) {
+#pragma unroll
+    for (int i = 0; i < P::E; ++i) v[i] = BufIO<T>::ld(r, voff, (unsigned)m_first<P>(i) * sstep);
+}
+
+template <typename T, class P>
+__device__ __forceinline__ void store_col(const cpx<T> (&v)[P::E], __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                          unsigned sstep, bool active) {
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < P::E; ++i) BufIO<T>::st(v[i], r, voff, (unsigned)m_last<P>(i) * sstep);
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// y pass: C2C along y, one component per workgroup
 // ---------------------------------------------------------------------------------
 template <typename T, class P, int B, bool INV>
 __global__ void __launch_bounds__(P::T * B)
-k_y(cpx<T>* __restrict__ buf, int M, int nz, const cpx<T>* __restrict__ twy) {
+k_y(cpx<T>* buf, int M, int nz, const cpx<T>* __restrict__ twy) {
     constexpr int NY = P::N, E = P::E, TT = P::T;
-    __shared__ T s_re[NY * B];
-    __shared__ T s_im[NY * B];
+    __shared__ T s_re[NY * (B + 1)];
+    __shared__ T s_im[NY * (B + 1)];
+    __shared__ cpx<T> s_tw[NY];
+    stage_table(s_tw, twy, NY);
     const int c = threadIdx.x % B, t = threadIdx.x / B;
     const int col = blockIdx.x * B + c;
     const int z = blockIdx.y;
     const int comp = blockIdx.z;
     const bool active = col < M;
-    cpx<T>* base = buf + ((long)comp * nz + z) * (long)NY * M + col;
+    const unsigned plane = (unsigned)(NY * M) * sizeof(cpx<T>);
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(buf + ((long)comp * nz + z) * (long)NY * M, plane);
+    const unsigned voff = (unsigned)(t * M + (active ? col : M - 1)) * sizeof(cpx<T>);
+    const unsigned sstep = (unsigned)(TT * M) * sizeof(cpx<T>);
     cpx<T> v[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = active ? base[(long)(t + TT * m_first<P>(i)) * M] : cpx<T>{0, 0};
+    load_col<T, P>(v, r, voff, sstep);
     LdsCols<T, B> lds{s_re, s_im, c};
-    fft_pencil<P, INV, 1>(v, t, lds, twy);
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < E; ++i) base[(long)(t + TT * m_last<P>(i)) * M] = v[i];
-    }
+    fft_pencil<P, INV, 1>(v, t, lds, s_tw);
+    store_col<T, P>(v, r, voff, sstep, active);
 }
 
 // ---------------------------------------------------------------------------------
 // z pass: forward z, propagate, invariant partials, inverse z (all six components)
 // ---------------------------------------------------------------------------------
 enum ZMode { Z_STEP = 0, Z_FORWARD = 1 };
-
-template <typename T, class P>
-__device__ __forceinline__ void load_col(cpx<T> (&v)[P::E], const cpx<T>* base, long stride, int t, bool active) {
-#pragma unroll
-    for (int i = 0; i < P::E; ++i) v[i] = active ? base[(long)(t + P::T * m_first<P>(i)) * stride] : cpx<T>{0, 0};
-}
-
-template <typename T, class P>
-__device__ __forceinline__ void store_col(const cpx<T> (&v)[P::E], cpx<T>* base, long stride, int t, bool active) {
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < P::E; ++i) base[(long)(t + P::T * m_last<P>(i)) * stride] = v[i];
-    }
-}
 
 template <typename T>
 __device__ __forceinline__ double dreal(T a) { return (double)a; }
@@ -173,7 +188,8 @@ __device__ __forceinline__ double dreal(T a) { return (double)a; }
 // discrete inner products of Sec. 4 (Parseval) with no further scaling.
 template <typename T>
 __device__ __forceinline__ void accumulate_invariants(double (&acc)[INV_NPART], double w, double bx, double by, double bz,
-                                                      const cpx<T>* h, const cpx<T>* e, double mu, double eps) {
+                                                      const cpx<T>* h, const cpx<T>* e, const PropParams& pp) {
+    const double mu = pp.mu, eps = pp.eps;
     const double hr[3] = {dreal(h[0].x), dreal(h[1].x), dreal(h[2].x)};
     const double hi[3] = {dreal(h[0].y), dreal(h[1].y), dreal(h[2].y)};
     const double er[3] = {dreal(e[0].x), dreal(e[1].x), dreal(e[2].x)};
@@ -190,7 +206,7 @@ __device__ __forceinline__ void accumulate_invariants(double (&acc)[INV_NPART], 
                       bz * (hr[0] * hi[1] - hr[1] * hi[0]);
     const double ec = bx * (er[1] * ei[2] - er[2] * ei[1]) + by * (er[2] * ei[0] - er[0] * ei[2]) +
                       bz * (er[0] * ei[1] - er[1] * ei[0]);
-    acc[INV_H1] += w * (hc / eps + ec / mu);
+    acc[INV_H1] += w * (hc * pp.inv_eps + ec * pp.inv_mu);
     // Im H . Re E - Re H . Im E
     double q = 0;
 #pragma unroll
@@ -216,7 +232,6 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[INV_NPART], dou
     }
     constexpr int NW = (NT + 63) / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();
     if (lane == 0) {
 #pragma unroll
         for (int q = 0; q < INV_NPART; ++q) s_red[wid * INV_NPART + q] = acc[q];
@@ -277,27 +292,46 @@ __device__ __forceinline__ void propagate_mode(cpx<T>* h, cpx<T>* e, double bx, 
     }
 }
 
+// Minimum waves per SIMD requested for the fused z kernel (caps its register budget).
+#ifndef EIFP_ZWAVES64
+#define EIFP_ZWAVES64 2
+#endif
+#ifndef EIFP_ZWAVES32
+#define EIFP_ZWAVES32 2
+#endif
+template <typename T> struct ZWaves { static constexpr int value = sizeof(T) == 8 ? EIFP_ZWAVES64 : EIFP_ZWAVES32; };
+
 template <typename T, class P, int B, int MODE>
-__global__ void __launch_bounds__(P::T * B)
-k_z(cpx<T>* __restrict__ buf, int M, int ny, long comp_stride, const cpx<T>* __restrict__ twz, PropParams pp,
+__global__ void __launch_bounds__(P::T * B, ZWaves<T>::value)
+k_z(cpx<T>* buf, int M, int ny, long comp_stride, const cpx<T>* __restrict__ twz, PropParams pp,
     double* __restrict__ partials, int want_inv) {
-    constexpr int NZ = P::N, E = P::E, TT = P::T;
-    __shared__ T s_re[NZ * B];
-    __shared__ T s_im[NZ * B];
-    __shared__ double s_red[((P::T * B + 63) / 64) * INV_NPART];
+    constexpr int NZ = P::N, E = P::E, TT = P::T, NT = P::T * B;
+    __shared__ T s_x[2 * 2 * NZ * (B + 1)];
+    __shared__ cpx<T> s_tw[NZ];
+    __shared__ double s_red[((NT + 63) / 64) * INV_NPART];
+    stage_table(s_tw, twz, NZ);
     const int c = threadIdx.x % B, t = threadIdx.x / B;
     const int col = blockIdx.x * B + c;
     const int y = blockIdx.y;
     const bool active = col < M;
-    const long zstride = (long)ny * M;
-    cpx<T>* base = buf + (long)y * M + col;
-    LdsCols<T, B> lds{s_re, s_im, c};
+    const unsigned cbytes = (unsigned)comp_stride * sizeof(cpx<T>);
+    const unsigned voff = (unsigned)(((long)t * ny + y) * M + (active ? col : M - 1)) * sizeof(cpx<T>);
+    const unsigned sstep = (unsigned)((long)TT * ny * M) * sizeof(cpx<T>);
+    LdsCols2<T, B, NZ * (B + 1)> lds{s_x, c, 0};
 
     cpx<T> v[6][E];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) load_col<T, P>(v[q], base + q * comp_stride, zstride, t, active);
+    for (int q = 0; q < 6; ++q) load_col<T, P>(v[q], make_rsrc(buf + q * comp_stride, cbytes), voff, sstep);
 #pragma unroll
-    for (int q = 0; q < 6; ++q) fft_pencil<P, false, 1>(v[q], t, lds, twz);
+    for (int q = 0; q < 6; ++q) {
+        // re-derive the lane indices per component so that LDS addresses are recomputed
+        // (cheap ALU) instead of being kept live across all twelve transforms
+        int tq = t, cq = c;
+        asm volatile("" : "+v"(tq), "+v"(cq));
+        lds.c = cq;
+        fft_pencil<P, false, 1>(v[q], tq, lds, s_tw);
+        __builtin_amdgcn_sched_barrier(0);  // one component's temporaries live at a time
+    }
 
     const double bx = col == 0 ? 0.0 : pp.nu[0] * (double)col;  // packed column: Omega_x = 0 at 0 and Nx/2
     const double by = omega(y, ny, pp.nu[1]);
@@ -321,7 +355,7 @@ k_z(cpx<T>* __restrict__ buf, int M, int ny, long comp_stride, const cpx<T>* __r
                 e[q] = scale(e[q], s);
             }
         }
-        if (want_inv && active) accumulate_invariants(acc, w, bx, by, bz, h, e, pp.mu, pp.eps);
+        if (want_inv && active) accumulate_invariants(acc, w, bx, by, bz, h, e, pp);
         if (MODE == Z_STEP) {
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
@@ -329,50 +363,56 @@ k_z(cpx<T>* __restrict__ buf, int M, int ny, long comp_stride, const cpx<T>* __r
                 v[3 + q][i] = e[q];
             }
         }
+        __builtin_amdgcn_sched_barrier(0);  // one mode's temporaries live at a time
     }
     if (want_inv) {
         const int nbx = gridDim.x;
-        block_reduce_store<P::T * B>(acc, partials + ((long)blockIdx.y * nbx + blockIdx.x) * INV_NPART, s_red);
+        block_reduce_store<NT>(acc, partials + ((long)blockIdx.y * nbx + blockIdx.x) * INV_NPART, s_red);
     }
     if (MODE == Z_STEP) {
-        // z^-1 then store; Z_FORWARD leaves the (scaled) spectrum untouched in memory
-        __syncthreads();
+        // z^-1 then store each component as soon as it is done; Z_FORWARD leaves memory untouched
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             last_to_first<P>(v[q]);
-            fft_pencil<P, true, 1>(v[q], t, lds, twz);
+            int tq = t, cq = c;
+            asm volatile("" : "+v"(tq), "+v"(cq));
+            lds.c = cq;
+            fft_pencil<P, true, 1>(v[q], tq, lds, s_tw);
+            store_col<T, P>(v[q], make_rsrc(buf + q * comp_stride, cbytes), voff, sstep, active);
+            __builtin_amdgcn_sched_barrier(0);
         }
-#pragma unroll
-        for (int q = 0; q < 6; ++q) store_col<T, P>(v[q], base + q * comp_stride, zstride, t, active);
     }
 }
 
 // Forward-only variant that stores the (unscaled) spectrum, for diagnostics.
 template <typename T, class P, int B>
 __global__ void __launch_bounds__(P::T * B)
-k_z_fwd_store(cpx<T>* __restrict__ buf, int M, int ny, long comp_stride, const cpx<T>* __restrict__ twz) {
-    constexpr int NZ = P::N, E = P::E;
-    __shared__ T s_re[NZ * B];
-    __shared__ T s_im[NZ * B];
+k_z_fwd_store(cpx<T>* buf, int M, int ny, long comp_stride, const cpx<T>* __restrict__ twz) {
+    constexpr int NZ = P::N, E = P::E, TT = P::T;
+    __shared__ T s_x[2 * 2 * NZ * (B + 1)];
+    __shared__ cpx<T> s_tw[NZ];
+    stage_table(s_tw, twz, NZ);
     const int c = threadIdx.x % B, t = threadIdx.x / B;
     const int col = blockIdx.x * B + c;
     const int y = blockIdx.y;
-    const bool active = col < M;
-    const long zstride = (long)ny * M;
-    LdsCols<T, B> lds{s_re, s_im, c};
     const int comp = blockIdx.z;
-    cpx<T>* base = buf + comp * comp_stride + (long)y * M + col;
+    const bool active = col < M;
+    const unsigned cbytes = (unsigned)comp_stride * sizeof(cpx<T>);
+    const unsigned voff = (unsigned)(((long)t * ny + y) * M + (active ? col : M - 1)) * sizeof(cpx<T>);
+    const unsigned sstep = (unsigned)((long)TT * ny * M) * sizeof(cpx<T>);
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(buf + comp * comp_stride, cbytes);
+    LdsCols2<T, B, NZ * (B + 1)> lds{s_x, c, 0};
     cpx<T> v[E];
-    load_col<T, P>(v, base, zstride, t, active);
-    fft_pencil<P, false, 1>(v, t, lds, twz);
-    store_col<T, P>(v, base, zstride, t, active);
+    load_col<T, P>(v, r, voff, sstep);
+    fft_pencil<P, false, 1>(v, t, lds, s_tw);
+    store_col<T, P>(v, r, voff, sstep, active);
 }
 
 // ---------------------------------------------------------------------------------
 // deterministic compensated finalize of the invariant partials
 // ---------------------------------------------------------------------------------
 // out: [0] E1 [1] H1 [2..4] M1 [5] ||div~(mu H)||_N [6] ||div~(eps E)||_N
-__global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ partials, int nparts, double* __restrict__ out);
+__global__ void __launch_bounds__(1024) k_finalize(const double* __restrict__ partials, int nparts, double* __restrict__ out);
 
 // FP64 <-> T conversion for upload / download of the state.
 template <typename TO, typename TI>

@@ -9,9 +9,16 @@ namespace eifp {
 template <int N> struct XYE { static constexpr int E = (N % 3 == 0) ? (N >= 12 ? 12 : N) : (N >= 16 ? 16 : N); };
 // values per thread for the fused z pass, which holds six components at once: 4 or 6
 // in FP64, 8 or 12 in FP32 (keeps the six pencils in registers without spilling)
+#ifndef EIFP_ZE64
+#define EIFP_ZE64 4
+#endif
+#ifndef EIFP_ZE32
+#define EIFP_ZE32 8
+#endif
 template <typename T, int N> struct ZE {
-    static constexpr int E = sizeof(T) == 8 ? ((N % 3 == 0) ? 6 : 4)
-                                            : ((N % 3 == 0) ? (N >= 12 ? 12 : N) : (N >= 8 ? 8 : N));
+    static constexpr int E2 = sizeof(T) == 8 ? EIFP_ZE64 : EIFP_ZE32;  // for powers of two
+    static constexpr int E = sizeof(T) == 8 ? ((N % 3 == 0) ? 6 : (N >= E2 ? E2 : N))
+                                            : ((N % 3 == 0) ? (N >= 12 ? 12 : N) : (N >= E2 ? E2 : N));
 };
 
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
@@ -25,11 +32,16 @@ template <typename T, int N> struct YCfg {
     using P = Plan<N, XYE<N>::E>;
     static constexpr int B = cmax(1, cmin(cmin(64, 256 / P::T), (64 * 1024) / (N * 2 * (int)sizeof(T))));
 };
+// Row segment (bytes along x) targeted by a z tile; the double-buffered exchange takes
+// 4 N B sizeof(T) bytes of LDS.
+#ifndef EIFP_ZROW_BYTES
+#define EIFP_ZROW_BYTES 128
+#endif
 template <typename T, int N> struct ZCfg {
     using P = Plan<N, ZE<T, N>::E>;
-    // at least 128-byte row segments along x, at most 1024 threads and 60 KB of LDS
-    static constexpr int B0 = cmin(64, cmax(128 / (2 * (int)sizeof(T)), 256 / P::T));
-    static constexpr int B = cmax(1, cmin(cmin(B0, 1024 / P::T), (60 * 1024) / (N * 2 * (int)sizeof(T))));
+    // row segments of EIFP_ZROW_BYTES along x, at most 1024 threads and 96 KB of LDS
+    static constexpr int B0 = cmin(64, cmax(EIFP_ZROW_BYTES / (2 * (int)sizeof(T)), 256 / P::T));
+    static constexpr int B = cmax(1, cmin(cmin(B0, 1024 / P::T), (96 * 1024) / (N * 4 * (int)sizeof(T))));
 };
 
 inline int check_launch() { return hipGetLastError() == hipSuccess ? kOk : kLaunchFailed; }

@@ -59,28 +59,48 @@ __device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
     s = t;
 }
 
-__global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ partials, int nparts,
-                                                  double* __restrict__ out) {
-    __shared__ double s_sum[256];
-    __shared__ double s_cmp[256];
-    double res[INV_NPART];
+// Thread j sums records j, j + 1024, ... (each record: INV_NPART contiguous doubles)
+// with Neumaier compensation, then the 1024 (sum, compensation) pairs are combined by a
+// fixed xor-butterfly inside each wave and a fixed loop over the 16 waves: the same
+// partials always give the same bits.
+__global__ void __launch_bounds__(1024) k_finalize(const double* __restrict__ partials, int nparts,
+                                                   double* __restrict__ out) {
+    __shared__ double s_w[16][2 * INV_NPART];
+    double s[INV_NPART], c[INV_NPART];
+#pragma unroll
+    for (int q = 0; q < INV_NPART; ++q) s[q] = c[q] = 0.0;
+    for (int j = threadIdx.x; j < nparts; j += 1024) {
+        const double* rec = partials + (long)j * INV_NPART;
+#pragma unroll
+        for (int q = 0; q < INV_NPART; ++q) neumaier_add(s[q], c[q], rec[q]);
+    }
+#pragma unroll
     for (int q = 0; q < INV_NPART; ++q) {
-        double s = 0.0, c = 0.0;
-        for (int j = threadIdx.x; j < nparts; j += 256) neumaier_add(s, c, partials[(long)j * INV_NPART + q]);
-        s_sum[threadIdx.x] = s;
-        s_cmp[threadIdx.x] = c;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) {
-                double a = s_sum[threadIdx.x], ca = s_cmp[threadIdx.x] + s_cmp[threadIdx.x + w];
-                neumaier_add(a, ca, s_sum[threadIdx.x + w]);
-                s_sum[threadIdx.x] = a;
-                s_cmp[threadIdx.x] = ca;
-            }
-            __syncthreads();
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double os = __shfl_xor(s[q], off, 64), oc = __shfl_xor(c[q], off, 64);
+            c[q] += oc;
+            neumaier_add(s[q], c[q], os);
         }
-        res[q] = s_sum[0] + s_cmp[0];
-        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < INV_NPART; ++q) {
+            s_w[wid][q] = s[q];
+            s_w[wid][INV_NPART + q] = c[q];
+        }
+    }
+    __syncthreads();
+    double res[INV_NPART];
+#pragma unroll
+    for (int q = 0; q < INV_NPART; ++q) {
+        double a = 0.0, ca = 0.0;
+        for (int w = 0; w < 16; ++w) {
+            ca += s_w[w][INV_NPART + q];
+            neumaier_add(a, ca, s_w[w][q]);
+        }
+        res[q] = a + ca;
     }
     if (threadIdx.x == 0) {
         out[0] = res[INV_E1];
@@ -156,6 +176,8 @@ PropParams make_params(const eifp_solver* s, double tau) {
     pp.nu[2] = two_pi / (s->dom.zr - s->dom.zl);
     pp.mu = s->mu;
     pp.eps = s->eps;
+    pp.inv_mu = 1.0 / s->mu;
+    pp.inv_eps = 1.0 / s->eps;
     return pp;
 }
 
@@ -187,7 +209,7 @@ eifp_status run_passes(eifp_solver* s, int mode, void* src, void* dst, double ta
         if ((rc = launch_x<T>(true, s->nx, dst, dst, rows, s->twx, s->stream))) return rc_to_status(rc, "x inverse");
         if (ev) HIP_TRY(hipEventRecord(ev[5], s->stream));
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s->stream, (const double*)s->partials, s->nparts,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s->stream, (const double*)s->partials, s->nparts,
                        s->inv_dev);
     if (hipGetLastError() != hipSuccess) return fail(EIFP_ERR_DEVICE, "finalize launch failed");
     if (ev) HIP_TRY(hipEventRecord(ev[6], s->stream));
