@@ -87,8 +87,9 @@ eifp_status eifp_step(eifp_solver *s, double tau, long long nsteps);
 
 /* Same as eifp_step, and also measures each pass with HIP events recorded on the
  * solver's stream around every kernel.  pass_ms[0..5] receive the summed durations in
- * milliseconds of: x-forward, y-forward, fused z (forward, propagator, invariant
- * partials, inverse), y-inverse, x-inverse, invariant finalize.  Synchronises the
+ * milliseconds of: x-forward (real-to-complex), z-forward, fused y (forward,
+ * propagator, invariant partials, inverse), z-inverse, x-inverse (complex-to-real),
+ * invariant finalize.  Synchronises the
  * stream before returning.  Errors as eifp_step, plus INVALID_ARG for NULL pass_ms. */
 eifp_status eifp_step_timed(eifp_solver *s, double tau, long long nsteps, double *pass_ms);
 

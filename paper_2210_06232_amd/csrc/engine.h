@@ -1,0 +1,76 @@
+// engine.h -- host-side pieces shared by the solver and the server: error text,
+// argument validation, the per-solve scalars, and the per-shape executor that launches
+// the pass sequence of one step for a batch of members.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "eifp.h"
+#include "passes.h"
+
+namespace eifp {
+
+// thread-local error text behind eifp_last_error()
+eifp_status fail(eifp_status st, const char* fmt, ...);
+void clear_error();
+const char* last_error();
+
+#define EIFP_HIP_TRY(expr)                                                                                       \
+    do {                                                                                                         \
+        hipError_t e_ = (expr);                                                                                  \
+        if (e_ != hipSuccess) return ::eifp::fail(EIFP_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// sizes: even, >= 4, factors 2 and 3 only, at most 512
+eifp_status validate_shape(int nx, int ny, int nz);
+// finite domain with right > left, mu and eps positive and finite
+eifp_status validate_problem(const eifp_domain* dom, double mu, double eps);
+// tau finite
+eifp_status validate_tau(double tau);
+
+// Per-solve scalars of the fused pass, formed in FP64 (Alg. 2 step 2: kappa = tau /
+// sqrt(mu eps); the sqrt(mu), sqrt(eps) scalings of step 4 as their ratios).
+PropParams make_params(int nx, int ny, int nz, const eifp_domain& dom, double mu, double eps, double tau);
+
+// Host image of one member descriptor; same layout as MemberDesc<T> for either T.
+struct DescImage {
+    void* state;
+    void* work;
+    double* partials;
+    double* inv;
+    PropParams pp;
+};
+static_assert(sizeof(DescImage) == sizeof(MemberDesc<double>), "descriptor layout");
+static_assert(sizeof(DescImage) == sizeof(MemberDesc<float>), "descriptor layout");
+
+// Executor for one grid shape and precision: twiddle tables (FP64-formed, rounded to the
+// working type) and the launch sequence.  Owns only the tables.
+struct Engine {
+    Grid3 g{};
+    eifp_precision prec = EIFP_FP64;
+    size_t tsize = 8;
+    long long ns = 0;
+    void* twx = nullptr;
+    void* twy = nullptr;
+    void* twz = nullptr;
+    int nparts = 0;  // partial records per member
+    long long bytes = 0;
+
+    eifp_status init(int nx, int ny, int nz, eifp_precision p);
+    void release();
+    size_t state_bytes() const { return (size_t)6 * (size_t)ns * tsize; }
+    size_t partial_bytes() const { return (size_t)nparts * INV_NPART * sizeof(double); }
+
+    // One step (mode Z_STEP: x, z, fused y, z^-1, x^-1, finalize) or a forward-only
+    // evaluation of the invariants (mode Z_FORWARD: state -> work, nothing stored back),
+    // for nm members described by the device array md.  ev: 7 events recorded around
+    // the kernels (or null).
+    eifp_status passes(int mode, const void* md, int nm, hipStream_t st, hipEvent_t* ev) const;
+    // unscaled forward transform of each member's state into its work buffer
+    eifp_status forward_spectrum(const void* md, int nm, hipStream_t st) const;
+};
+
+// Widen / narrow n reals on the device (enqueued on st).
+eifp_status convert_f32_to_f64(const void* in, void* out, long long n, hipStream_t st);
+eifp_status convert_f64_to_f32(const void* in, void* out, long long n, hipStream_t st);
+
+}  // namespace eifp

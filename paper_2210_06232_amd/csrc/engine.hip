@@ -1,0 +1,193 @@
+// engine.hip -- error text, validation, per-solve scalars and the per-shape executor.
+#include "engine.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+namespace eifp {
+
+namespace {
+thread_local std::string g_err;
+
+bool only_2_3(int n) {
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+template <typename T>
+eifp_status upload_table(void** dst, int n, long long* bytes) {
+    // exp(-2 pi i k / n), k < n, formed in FP64 and rounded to T
+    std::vector<T> h(2 * (size_t)n);
+    for (int k = 0; k < n; ++k) {
+        const double a = kTwoPi * (double)k / (double)n;
+        h[2 * k] = (T)std::cos(a);
+        h[2 * k + 1] = (T)-std::sin(a);
+    }
+    if (hipMalloc(dst, h.size() * sizeof(T)) != hipSuccess) {
+        *dst = nullptr;
+        (void)hipGetLastError();
+        return fail(EIFP_ERR_OUT_OF_MEMORY, "twiddle table allocation failed");
+    }
+    *bytes += (long long)(h.size() * sizeof(T));
+    EIFP_HIP_TRY(hipMemcpy(*dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return EIFP_OK;
+}
+
+eifp_status rc_to_status(int rc, const char* what) {
+    if (rc == kOk) return EIFP_OK;
+    if (rc == kUnsupported) return fail(EIFP_ERR_UNSUPPORTED_SIZE, "%s: no compiled plan for this size", what);
+    return fail(EIFP_ERR_DEVICE, "%s: kernel launch failed: %s", what, hipGetErrorString(hipGetLastError()));
+}
+
+template <typename T>
+eifp_status run_passes(const Engine& en, int mode, const void* md, int nm, hipStream_t st, hipEvent_t* ev) {
+    int rc;
+    if (ev) EIFP_HIP_TRY(hipEventRecord(ev[0], st));
+    if ((rc = launch_x<T>(false, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x forward");
+    if (ev) EIFP_HIP_TRY(hipEventRecord(ev[1], st));
+    if ((rc = launch_c2c<T>(false, AXIS_Z, en.g, md, nm, en.twz, st))) return rc_to_status(rc, "z forward");
+    if (ev) EIFP_HIP_TRY(hipEventRecord(ev[2], st));
+    if ((rc = launch_fused<T>(mode, AXIS_Y, en.g, md, nm, en.twy, 1, st))) return rc_to_status(rc, "fused y pass");
+    if (ev) EIFP_HIP_TRY(hipEventRecord(ev[3], st));
+    if (mode == Z_STEP) {
+        if ((rc = launch_c2c<T>(true, AXIS_Z, en.g, md, nm, en.twz, st))) return rc_to_status(rc, "z inverse");
+        if (ev) EIFP_HIP_TRY(hipEventRecord(ev[4], st));
+        if ((rc = launch_x<T>(true, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x inverse");
+        if (ev) EIFP_HIP_TRY(hipEventRecord(ev[5], st));
+    } else if (ev) {
+        EIFP_HIP_TRY(hipEventRecord(ev[4], st));
+        EIFP_HIP_TRY(hipEventRecord(ev[5], st));
+    }
+    if ((rc = launch_finalize<T>(md, nm, en.nparts, st))) return rc_to_status(rc, "finalize");
+    if (ev) EIFP_HIP_TRY(hipEventRecord(ev[6], st));
+    return EIFP_OK;
+}
+
+template <typename T>
+eifp_status run_spectrum(const Engine& en, const void* md, int nm, hipStream_t st) {
+    int rc;
+    if ((rc = launch_x<T>(false, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x forward");
+    if ((rc = launch_c2c<T>(false, AXIS_Z, en.g, md, nm, en.twz, st))) return rc_to_status(rc, "z forward");
+    if ((rc = launch_c2c<T>(false, AXIS_Y, en.g, md, nm, en.twy, st))) return rc_to_status(rc, "y forward");
+    return EIFP_OK;
+}
+
+template <typename TO, typename TI>
+eifp_status convert(const void* in, void* out, long long n, hipStream_t st) {
+    const long long blocks = (n + 255) / 256;
+    const unsigned grid = (unsigned)(blocks < 65536 ? (blocks > 0 ? blocks : 1) : 65536);
+    hipLaunchKernelGGL((k_convert<TO, TI>), dim3(grid), dim3(256), 0, st, (const TI*)in, (TO*)out, (long)n);
+    if (hipGetLastError() != hipSuccess) return fail(EIFP_ERR_DEVICE, "conversion kernel launch failed");
+    return EIFP_OK;
+}
+
+}  // namespace
+
+eifp_status fail(eifp_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+void clear_error() { g_err.clear(); }
+
+const char* last_error() { return g_err.c_str(); }
+
+eifp_status validate_shape(int nx, int ny, int nz) {
+    const int n3[3] = {nx, ny, nz};
+    for (int w = 0; w < 3; ++w) {
+        if (n3[w] < 4 || n3[w] % 2) return fail(EIFP_ERR_INVALID_ARG, "grid size %d must be even and >= 4", n3[w]);
+        if (!only_2_3(n3[w]) || n3[w] > 512)
+            return fail(EIFP_ERR_UNSUPPORTED_SIZE, "grid size %d: only 2^a 3^b up to 512 are supported", n3[w]);
+    }
+    return EIFP_OK;
+}
+
+eifp_status validate_problem(const eifp_domain* dom, double mu, double eps) {
+    if (!dom) return fail(EIFP_ERR_INVALID_ARG, "NULL domain");
+    const double lo[3] = {dom->xl, dom->yl, dom->zl}, hi[3] = {dom->xr, dom->yr, dom->zr};
+    for (int w = 0; w < 3; ++w)
+        if (!std::isfinite(lo[w]) || !std::isfinite(hi[w]) || !(hi[w] > lo[w]))
+            return fail(EIFP_ERR_INVALID_ARG, "domain axis %d: need finite bounds with right > left", w);
+    if (!(mu > 0) || !(eps > 0) || !std::isfinite(mu) || !std::isfinite(eps))
+        return fail(EIFP_ERR_INVALID_ARG, "mu and eps must be positive and finite");
+    return EIFP_OK;
+}
+
+eifp_status validate_tau(double tau) {
+    if (!std::isfinite(tau)) return fail(EIFP_ERR_INVALID_ARG, "tau must be finite");
+    return EIFP_OK;
+}
+
+PropParams make_params(int nx, int ny, int nz, const eifp_domain& dom, double mu, double eps, double tau) {
+    PropParams pp;
+    pp.tau_s = tau / std::sqrt(mu * eps);
+    pp.tau_s_over_pi = pp.tau_s / kPi;
+    pp.rh = std::sqrt(mu / eps);
+    pp.re = std::sqrt(eps / mu);
+    pp.inv_ns = 1.0 / ((double)nx * (double)ny * (double)nz);
+    pp.nu[0] = kTwoPi / (dom.xr - dom.xl);
+    pp.nu[1] = kTwoPi / (dom.yr - dom.yl);
+    pp.nu[2] = kTwoPi / (dom.zr - dom.zl);
+    pp.mu = mu;
+    pp.eps = eps;
+    pp.inv_mu = 1.0 / mu;
+    pp.inv_eps = 1.0 / eps;
+    return pp;
+}
+
+eifp_status Engine::init(int nx, int ny, int nz, eifp_precision p) {
+    g = Grid3{nx, ny, nz, nx / 2};
+    prec = p;
+    tsize = p == EIFP_FP64 ? 8 : 4;
+    ns = (long long)nx * ny * nz;
+    nparts = p == EIFP_FP64 ? fused_partial_count<double>(AXIS_Y, g) : fused_partial_count<float>(AXIS_Y, g);
+    if (nparts <= 0) return fail(EIFP_ERR_UNSUPPORTED_SIZE, "no compiled plan for ny = %d", ny);
+    eifp_status st = EIFP_OK;
+    if (p == EIFP_FP64) {
+        if ((st = upload_table<double>(&twx, nx, &bytes)) || (st = upload_table<double>(&twy, ny, &bytes)) ||
+            (st = upload_table<double>(&twz, nz, &bytes)))
+            return st;
+    } else {
+        if ((st = upload_table<float>(&twx, nx, &bytes)) || (st = upload_table<float>(&twy, ny, &bytes)) ||
+            (st = upload_table<float>(&twz, nz, &bytes)))
+            return st;
+    }
+    return EIFP_OK;
+}
+
+void Engine::release() {
+    for (void* q : {twx, twy, twz})
+        if (q) (void)hipFree(q);
+    twx = twy = twz = nullptr;
+}
+
+eifp_status Engine::passes(int mode, const void* md, int nm, hipStream_t st, hipEvent_t* ev) const {
+    return prec == EIFP_FP64 ? run_passes<double>(*this, mode, md, nm, st, ev)
+                             : run_passes<float>(*this, mode, md, nm, st, ev);
+}
+
+eifp_status Engine::forward_spectrum(const void* md, int nm, hipStream_t st) const {
+    return prec == EIFP_FP64 ? run_spectrum<double>(*this, md, nm, st) : run_spectrum<float>(*this, md, nm, st);
+}
+
+eifp_status convert_f32_to_f64(const void* in, void* out, long long n, hipStream_t st) {
+    return convert<double, float>(in, out, n, st);
+}
+
+eifp_status convert_f64_to_f32(const void* in, void* out, long long n, hipStream_t st) {
+    return convert<float, double>(in, out, n, st);
+}
+
+}  // namespace eifp

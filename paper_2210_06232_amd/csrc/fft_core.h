@@ -288,9 +288,13 @@ __device__ __forceinline__ void fft_pencil(cpx<T> (&v)[P::E], int t, Lds& lds, c
 
 // LDS views.  Columns: a tile of B pencils stored [pos][col] (real and imaginary parts
 // in separate planes), so the B lanes of one position hit consecutive banks.
-// Rows of the [pos][col] views have a pitch of B + 1 elements: positions that differ by
-// a power of two then fall in different LDS banks (a pitch of B would put the lanes of a
-// wave that share a column on the same banks).
+// Rows of the [pos][col] views have a pitch of B + pad elements: positions that differ
+// by a power of two then fall in different LDS banks (a pitch of B would put the lanes of
+// a wave that share a column on the same banks).
+#ifndef EIFP_LDS_PAD
+#define EIFP_LDS_PAD 1
+#endif
+__host__ __device__ constexpr int col_pitch(int B) { return B + EIFP_LDS_PAD; }
 // after_load(): a single buffer needs a second barrier before it is written again; the
 // double-buffered views flip to the other buffer instead, which is safe because the
 // next write to this buffer comes after the next exchange's barrier.
@@ -299,8 +303,8 @@ struct LdsCols {
     T* re;
     T* im;
     int c;
-    __device__ __forceinline__ void st(int pos, cpx<T> a) { re[pos * (B + 1) + c] = a.x; im[pos * (B + 1) + c] = a.y; }
-    __device__ __forceinline__ cpx<T> ld(int pos) const { return {re[pos * (B + 1) + c], im[pos * (B + 1) + c]}; }
+    __device__ __forceinline__ void st(int pos, cpx<T> a) { re[pos * col_pitch(B) + c] = a.x; im[pos * col_pitch(B) + c] = a.y; }
+    __device__ __forceinline__ cpx<T> ld(int pos) const { return {re[pos * col_pitch(B) + c], im[pos * col_pitch(B) + c]}; }
     __device__ __forceinline__ void sync() { __syncthreads(); }
     __device__ __forceinline__ void after_load() { __syncthreads(); }
 };
@@ -315,12 +319,12 @@ struct LdsCols2 {
     __device__ __forceinline__ T* re() const { return base + (2 * cur) * PLANE; }
     __device__ __forceinline__ void st(int pos, cpx<T> a) {
         T* r = re();
-        r[pos * (B + 1) + c] = a.x;
-        r[PLANE + pos * (B + 1) + c] = a.y;
+        r[pos * col_pitch(B) + c] = a.x;
+        r[PLANE + pos * col_pitch(B) + c] = a.y;
     }
     __device__ __forceinline__ cpx<T> ld(int pos) const {
         const T* r = re();
-        return {r[pos * (B + 1) + c], r[PLANE + pos * (B + 1) + c]};
+        return {r[pos * col_pitch(B) + c], r[PLANE + pos * col_pitch(B) + c]};
     }
     __device__ __forceinline__ void sync() { __syncthreads(); }
     __device__ __forceinline__ void after_load() { cur ^= 1; }

@@ -10,26 +10,44 @@
 //            so the kx = 0 and kx = Nx/2 planes see the same propagator; the packed
 //            column is therefore propagated and transformed along y and z as one
 //            complex column with no unpacking.
-//   y pass   C2C along y on tiles of B adjacent columns (coalesced along x).
-//   z pass   fused: C2C along z for all six components of a tile, the mode-wise
+//   z pass   C2C along z, one component per workgroup, tiles of B adjacent x columns.
+//   y pass   fused: C2C along y for all six components of a tile, the mode-wise
 //            exponential propagator (Prop. 2.1/2.2, Alg. 2 step 4) with the 1/(Nx Ny Nz)
 //            of the inverse transform folded in, the invariant partial sums, and the
-//            inverse C2C along z.
-//   y^-1, x^-1 as above in reverse (complex-to-real split back).
+//            inverse C2C along y.
+//   z^-1, x^-1 as above in reverse (complex-to-real merge back).
+//
+// Every kernel works on a batch of solves of one shape ("members"): the member index
+// comes from the grid and selects a descriptor (buffers and per-solve scalars) from a
+// device array, so one launch advances every member of a batch.
 #pragma once
 #include "fft_core.h"
 
 namespace eifp {
 
-// Per-step scalars for the z pass (formed in FP64 on the host).
+// Per-solve scalars of the fused pass (formed in FP64 on the host).
 struct PropParams {
-    double tau_s;      // tau / sqrt(mu eps)
-    double rh;         // sqrt(mu / eps): weight of i k x H^ in E^'
-    double re;         // sqrt(eps / mu): weight of i k x E^ in H^'
-    double inv_ns;     // 1 / (Nx Ny Nz)
-    double nu[3];      // 2 pi / L_w
+    double tau_s;          // tau / sqrt(mu eps)
+    double tau_s_over_pi;  // tau / (pi sqrt(mu eps))
+    double rh;             // sqrt(mu / eps): weight of i k x H^ in E^'
+    double re;             // sqrt(eps / mu): weight of i k x E^ in H^'
+    double inv_ns;         // 1 / (Nx Ny Nz)
+    double nu[3];          // 2 pi / L_w
     double mu, eps;
     double inv_mu, inv_eps;
+};
+
+// One member of a batch.  state: the solve's six fields (x-forward source, x-inverse
+// destination); work: the buffer the transforms run in (== state for a step, a scratch
+// buffer for a forward-only evaluation); partials: ntiles records of INV_NPART doubles;
+// inv: the finalized invariants (8 doubles).
+template <typename T>
+struct MemberDesc {
+    cpx<T>* state;
+    cpx<T>* work;
+    double* partials;
+    double* inv;
+    PropParams pp;
 };
 
 // invariant partial sums per workgroup (all in FP64)
@@ -45,14 +63,17 @@ __device__ __forceinline__ double omega(int m, int n, double nu) {
 // x pass: real <-> packed half spectrum along contiguous rows
 // ---------------------------------------------------------------------------------
 // twx[k] = exp(-2 pi i k / Nx), k < Nx (the length-M FFT reads every second entry).
+// Grid: (row blocks, members).  Forward reads state, writes work.
 template <typename T, class P, int NP>
 __global__ void __launch_bounds__(P::T * NP)
-k_x_fwd(const cpx<T>* src, cpx<T>* dst, long nrows, const cpx<T>* __restrict__ twx) {
+k_x_fwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restrict__ twx) {
     constexpr int M = P::N, E = P::E, TT = P::T, LD = M + 1;
     __shared__ T s_re[NP * LD];
     __shared__ T s_im[NP * LD];
     __shared__ cpx<T> s_tw[2 * M];
     stage_table(s_tw, twx, 2 * M);
+    const cpx<T>* src = md[blockIdx.y].state;
+    cpx<T>* dst = md[blockIdx.y].work;
     const int t = threadIdx.x % TT, p = threadIdx.x / TT;
     const long row = (long)blockIdx.x * NP + p;
     const bool active = row < nrows;
@@ -86,14 +107,17 @@ k_x_fwd(const cpx<T>* src, cpx<T>* dst, long nrows, const cpx<T>* __restrict__ t
     }
 }
 
+// Inverse reads work, writes state.
 template <typename T, class P, int NP>
 __global__ void __launch_bounds__(P::T * NP)
-k_x_inv(const cpx<T>* src, cpx<T>* dst, long nrows, const cpx<T>* __restrict__ twx) {
+k_x_inv(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restrict__ twx) {
     constexpr int M = P::N, E = P::E, TT = P::T, LD = M + 1;
     __shared__ T s_re[NP * LD];
     __shared__ T s_im[NP * LD];
     __shared__ cpx<T> s_tw[2 * M];
     stage_table(s_tw, twx, 2 * M);
+    const cpx<T>* src = md[blockIdx.y].work;
+    cpx<T>* dst = md[blockIdx.y].state;
     const int t = threadIdx.x % TT, p = threadIdx.x / TT;
     const long row = (long)blockIdx.x * NP + p;
     const bool active = row < nrows;
@@ -149,25 +173,28 @@ __device__ __forceinline__ void store_col(const cpx<T> (&v)[P::E], __amdgpu_buff
 }
 
 // ---------------------------------------------------------------------------------
-// y pass: C2C along y, one component per workgroup
+// single-component C2C pass along a strided axis (y or z), one component per workgroup
 // ---------------------------------------------------------------------------------
+// Pencil positions are pstride apart; the third (outer) axis index blockIdx.y is ostride
+// apart; cs is the component stride; all in complex elements.  Grid: (x tiles, outer,
+// 6 x members); runs in place on work.
 template <typename T, class P, int B, bool INV>
 __global__ void __launch_bounds__(P::T * B)
-k_y(cpx<T>* buf, int M, int nz, const cpx<T>* __restrict__ twy) {
-    constexpr int NY = P::N, E = P::E, TT = P::T;
-    __shared__ T s_re[NY * (B + 1)];
-    __shared__ T s_im[NY * (B + 1)];
-    __shared__ cpx<T> s_tw[NY];
-    stage_table(s_tw, twy, NY);
+k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, long cs,
+      const cpx<T>* __restrict__ tw) {
+    constexpr int NP = P::N, E = P::E, TT = P::T;
+    __shared__ T s_re[NP * col_pitch(B)];
+    __shared__ T s_im[NP * col_pitch(B)];
+    __shared__ cpx<T> s_tw[NP];
+    stage_table(s_tw, tw, NP);
     const int c = threadIdx.x % B, t = threadIdx.x / B;
     const int col = blockIdx.x * B + c;
-    const int z = blockIdx.y;
-    const int comp = blockIdx.z;
+    const int o = blockIdx.y;
+    const int member = blockIdx.z / 6, comp = blockIdx.z % 6;
     const bool active = col < M;
-    const unsigned plane = (unsigned)(NY * M) * sizeof(cpx<T>);
-    const __amdgpu_buffer_rsrc_t r = make_rsrc(buf + ((long)comp * nz + z) * (long)NY * M, plane);
-    const unsigned voff = (unsigned)(t * M + (active ? col : M - 1)) * sizeof(cpx<T>);
-    const unsigned sstep = (unsigned)(TT * M) * sizeof(cpx<T>);
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(md[member].work + comp * cs, (unsigned)(cs * sizeof(cpx<T>)));
+    const unsigned voff = (unsigned)(t * pstride + o * ostride + (active ? col : M - 1)) * sizeof(cpx<T>);
+    const unsigned sstep = (unsigned)(TT * pstride) * sizeof(cpx<T>);
     cpx<T> v[E];
     load_col<T, P>(v, r, voff, sstep);
     LdsCols<T, B> lds{s_re, s_im, c};
@@ -176,7 +203,7 @@ k_y(cpx<T>* buf, int M, int nz, const cpx<T>* __restrict__ twy) {
 }
 
 // ---------------------------------------------------------------------------------
-// z pass: forward z, propagate, invariant partials, inverse z (all six components)
+// fused pass: forward, propagate, invariant partials, inverse (all six components)
 // ---------------------------------------------------------------------------------
 enum ZMode { Z_STEP = 0, Z_FORWARD = 1 };
 
@@ -253,20 +280,13 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[INV_NPART], dou
 // All coefficients are formed in FP64 and rounded to T; everything is scaled by 1/N_S.
 template <typename T>
 __device__ __forceinline__ void propagate_mode(cpx<T>* h, cpx<T>* e, double bx, double by, double bz, const PropParams& pp) {
+    // |b| = 0 needs no branch: theta = 0 gives cos = 1, sin = 0 and the k terms drop out
     const double b2 = bx * bx + by * by + bz * bz;
-    if (b2 == 0.0) {
-        const T s = (T)pp.inv_ns;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            h[c] = scale(h[c], s);
-            e[c] = scale(e[c], s);
-        }
-        return;
-    }
     const double bn = sqrt(b2);
-    const double ib = 1.0 / bn;
+    const double ib = b2 > 0.0 ? 1.0 / bn : 0.0;
+    // the phase in half-turns, theta / pi, so that the reduction is exact for any tau
     double sn, cs;
-    sincos(pp.tau_s * bn, &sn, &cs);
+    sincospi(pp.tau_s_over_pi * bn, &sn, &cs);
     const T kx = (T)(bx * ib), ky = (T)(by * ib), kz = (T)(bz * ib);
     const T cT = (T)(cs * pp.inv_ns);                 // transverse part
     const T dL = (T)((1.0 - cs) * pp.inv_ns);         // longitudinal minus transverse
@@ -292,7 +312,7 @@ __device__ __forceinline__ void propagate_mode(cpx<T>* h, cpx<T>* e, double bx, 
     }
 }
 
-// Minimum waves per SIMD requested for the fused z kernel (caps its register budget).
+// Minimum waves per SIMD requested for the fused kernel (caps its register budget).
 #ifndef EIFP_ZWAVES64
 #define EIFP_ZWAVES64 2
 #endif
@@ -301,27 +321,35 @@ __device__ __forceinline__ void propagate_mode(cpx<T>* h, cpx<T>* e, double bx, 
 #endif
 template <typename T> struct ZWaves { static constexpr int value = sizeof(T) == 8 ? EIFP_ZWAVES64 : EIFP_ZWAVES32; };
 
-template <typename T, class P, int B, int MODE>
+// The fused pass transforms, propagates and transforms back along one strided axis.
+// AXIS = 1: pencils along y (stride M), one tile row per z index; AXIS = 2: pencils along
+// z (stride Ny M), one tile row per y index.  Strides in complex elements; cs is the
+// component stride.  Grid: (x tiles, outer, members); each block writes one partial
+// record, at index blockIdx.y * gridDim.x + blockIdx.x of its member's partials.
+template <typename T, class P, int B, int MODE, int AXIS>
 __global__ void __launch_bounds__(P::T * B, ZWaves<T>::value)
-k_z(cpx<T>* buf, int M, int ny, long comp_stride, const cpx<T>* __restrict__ twz, PropParams pp,
-    double* __restrict__ partials, int want_inv) {
+k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, long ostride, long cs,
+        const cpx<T>* __restrict__ tw, int want_inv) {
     constexpr int NZ = P::N, E = P::E, TT = P::T, NT = P::T * B;
-    __shared__ T s_x[2 * 2 * NZ * (B + 1)];
+    __shared__ T s_x[2 * 2 * NZ * col_pitch(B)];
     __shared__ cpx<T> s_tw[NZ];
     __shared__ double s_red[((NT + 63) / 64) * INV_NPART];
-    stage_table(s_tw, twz, NZ);
+    stage_table(s_tw, tw, NZ);
+    const MemberDesc<T>& mem = md[blockIdx.z];
+    const PropParams pp = mem.pp;
+    cpx<T>* buf = mem.work;
     const int c = threadIdx.x % B, t = threadIdx.x / B;
     const int col = blockIdx.x * B + c;
-    const int y = blockIdx.y;
+    const int o = blockIdx.y;
     const bool active = col < M;
-    const unsigned cbytes = (unsigned)comp_stride * sizeof(cpx<T>);
-    const unsigned voff = (unsigned)(((long)t * ny + y) * M + (active ? col : M - 1)) * sizeof(cpx<T>);
-    const unsigned sstep = (unsigned)((long)TT * ny * M) * sizeof(cpx<T>);
-    LdsCols2<T, B, NZ * (B + 1)> lds{s_x, c, 0};
+    const unsigned cbytes = (unsigned)cs * sizeof(cpx<T>);
+    const unsigned voff = (unsigned)(t * pstride + o * ostride + (active ? col : M - 1)) * sizeof(cpx<T>);
+    const unsigned sstep = (unsigned)(TT * pstride) * sizeof(cpx<T>);
+    LdsCols2<T, B, NZ * col_pitch(B)> lds{s_x, c, 0};
 
     cpx<T> v[6][E];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) load_col<T, P>(v[q], make_rsrc(buf + q * comp_stride, cbytes), voff, sstep);
+    for (int q = 0; q < 6; ++q) load_col<T, P>(v[q], make_rsrc(buf + q * cs, cbytes), voff, sstep);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         // re-derive the lane indices per component so that LDS addresses are recomputed
@@ -334,15 +362,17 @@ k_z(cpx<T>* buf, int M, int ny, long comp_stride, const cpx<T>* __restrict__ twz
     }
 
     const double bx = col == 0 ? 0.0 : pp.nu[0] * (double)col;  // packed column: Omega_x = 0 at 0 and Nx/2
-    const double by = omega(y, ny, pp.nu[1]);
+    const double bo = omega(o, n_outer, AXIS == 1 ? pp.nu[2] : pp.nu[1]);
     double acc[INV_NPART];
 #pragma unroll
     for (int q = 0; q < INV_NPART; ++q) acc[q] = 0.0;
     const double w = col == 0 ? 1.0 : 2.0;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-        const int kz = t + TT * m_last<P>(i);
-        const double bz = omega(kz, NZ, pp.nu[2]);
+        const int kp = t + TT * m_last<P>(i);
+        const double bp = omega(kp, NZ, AXIS == 1 ? pp.nu[1] : pp.nu[2]);
+        const double by = AXIS == 1 ? bp : bo;
+        const double bz = AXIS == 1 ? bo : bp;
         cpx<T> h[3] = {v[0][i], v[1][i], v[2][i]};
         cpx<T> e[3] = {v[3][i], v[4][i], v[5][i]};
         if (MODE == Z_STEP) {
@@ -365,12 +395,11 @@ k_z(cpx<T>* buf, int M, int ny, long comp_stride, const cpx<T>* __restrict__ twz
         }
         __builtin_amdgcn_sched_barrier(0);  // one mode's temporaries live at a time
     }
-    if (want_inv) {
-        const int nbx = gridDim.x;
-        block_reduce_store<NT>(acc, partials + ((long)blockIdx.y * nbx + blockIdx.x) * INV_NPART, s_red);
-    }
+    if (want_inv)
+        block_reduce_store<NT>(acc, mem.partials + ((long)blockIdx.y * gridDim.x + blockIdx.x) * INV_NPART, s_red);
     if (MODE == Z_STEP) {
-        // z^-1 then store each component as soon as it is done; Z_FORWARD leaves memory untouched
+        // inverse transform and store each component as soon as it is done; Z_FORWARD
+        // leaves memory untouched
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             last_to_first<P>(v[q]);
@@ -378,41 +407,79 @@ k_z(cpx<T>* buf, int M, int ny, long comp_stride, const cpx<T>* __restrict__ twz
             asm volatile("" : "+v"(tq), "+v"(cq));
             lds.c = cq;
             fft_pencil<P, true, 1>(v[q], tq, lds, s_tw);
-            store_col<T, P>(v[q], make_rsrc(buf + q * comp_stride, cbytes), voff, sstep, active);
+            store_col<T, P>(v[q], make_rsrc(buf + q * cs, cbytes), voff, sstep, active);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
 
-// Forward-only variant that stores the (unscaled) spectrum, for diagnostics.
-template <typename T, class P, int B>
-__global__ void __launch_bounds__(P::T * B)
-k_z_fwd_store(cpx<T>* buf, int M, int ny, long comp_stride, const cpx<T>* __restrict__ twz) {
-    constexpr int NZ = P::N, E = P::E, TT = P::T;
-    __shared__ T s_x[2 * 2 * NZ * (B + 1)];
-    __shared__ cpx<T> s_tw[NZ];
-    stage_table(s_tw, twz, NZ);
-    const int c = threadIdx.x % B, t = threadIdx.x / B;
-    const int col = blockIdx.x * B + c;
-    const int y = blockIdx.y;
-    const int comp = blockIdx.z;
-    const bool active = col < M;
-    const unsigned cbytes = (unsigned)comp_stride * sizeof(cpx<T>);
-    const unsigned voff = (unsigned)(((long)t * ny + y) * M + (active ? col : M - 1)) * sizeof(cpx<T>);
-    const unsigned sstep = (unsigned)((long)TT * ny * M) * sizeof(cpx<T>);
-    const __amdgpu_buffer_rsrc_t r = make_rsrc(buf + comp * comp_stride, cbytes);
-    LdsCols2<T, B, NZ * (B + 1)> lds{s_x, c, 0};
-    cpx<T> v[E];
-    load_col<T, P>(v, r, voff, sstep);
-    fft_pencil<P, false, 1>(v, t, lds, s_tw);
-    store_col<T, P>(v, r, voff, sstep, active);
-}
-
 // ---------------------------------------------------------------------------------
 // deterministic compensated finalize of the invariant partials
 // ---------------------------------------------------------------------------------
-// out: [0] E1 [1] H1 [2..4] M1 [5] ||div~(mu H)||_N [6] ||div~(eps E)||_N
-__global__ void __launch_bounds__(1024) k_finalize(const double* __restrict__ partials, int nparts, double* __restrict__ out);
+// Grid: one block per member.  out (member's inv): [0] E1 [1] H1 [2..4] M1
+// [5] ||div~(mu H)||_N [6] ||div~(eps E)||_N
+__device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
+    const double t = s + x;
+    c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+}
+
+// Thread j sums records j, j + 1024, ... (each record: INV_NPART contiguous doubles)
+// with Neumaier compensation, then the 1024 (sum, compensation) pairs are combined by a
+// fixed xor-butterfly inside each wave and a fixed loop over the 16 waves: the same
+// partials always give the same bits.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_finalize(const MemberDesc<T>* __restrict__ md, int nparts) {
+    __shared__ double s_w[16][2 * INV_NPART];
+    const double* partials = md[blockIdx.x].partials;
+    double s[INV_NPART], c[INV_NPART];
+#pragma unroll
+    for (int q = 0; q < INV_NPART; ++q) s[q] = c[q] = 0.0;
+    for (int j = threadIdx.x; j < nparts; j += 1024) {
+        const double* rec = partials + (long)j * INV_NPART;
+#pragma unroll
+        for (int q = 0; q < INV_NPART; ++q) neumaier_add(s[q], c[q], rec[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < INV_NPART; ++q) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double os = __shfl_xor(s[q], off, 64), oc = __shfl_xor(c[q], off, 64);
+            c[q] += oc;
+            neumaier_add(s[q], c[q], os);
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < INV_NPART; ++q) {
+            s_w[wid][q] = s[q];
+            s_w[wid][INV_NPART + q] = c[q];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double res[INV_NPART];
+#pragma unroll
+        for (int q = 0; q < INV_NPART; ++q) {
+            double a = 0.0, ca = 0.0;
+            for (int w = 0; w < 16; ++w) {
+                ca += s_w[w][INV_NPART + q];
+                neumaier_add(a, ca, s_w[w][q]);
+            }
+            res[q] = a + ca;
+        }
+        double* out = md[blockIdx.x].inv;
+        out[0] = res[INV_E1];
+        out[1] = res[INV_H1];
+        out[2] = res[INV_M1X];
+        out[3] = res[INV_M1Y];
+        out[4] = res[INV_M1Z];
+        out[5] = sqrt(res[INV_DIVH]);
+        out[6] = sqrt(res[INV_DIVE]);
+        out[7] = 0.0;
+    }
+}
 
 // FP64 <-> T conversion for upload / download of the state.
 template <typename TO, typename TI>

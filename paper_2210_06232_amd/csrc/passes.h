@@ -1,6 +1,15 @@
 // passes.h -- host-side launchers for the per-precision pass kernels.  Each launcher
 // maps a runtime axis length to the compiled plan for it; unsupported lengths return
 // kUnsupported without launching anything.
+//
+// Pass order of one step: x forward (R2C split, rows), z forward (C2C, single component),
+// fused y (forward, propagator, invariant partials, inverse; all six components),
+// z inverse, x inverse (C2R merge), invariant finalize.  The fused pass runs along y
+// because its pencils are then M complex elements apart, while the strided z axis is
+// handled by the single-component pass, which can use wide tiles.
+//
+// Every launcher advances a batch of nm members of one shape; md is a device array of
+// nm member descriptors (see kernels.h).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -9,26 +18,33 @@
 namespace eifp {
 
 enum LaunchRc { kOk = 0, kUnsupported = 2, kLaunchFailed = 4 };
+enum Axis { AXIS_Y = 1, AXIS_Z = 2 };
 
-// Supported axis lengths: 2^a 3^b between 4 and 512 whose plans are compiled below.
-bool supported_axis(int n);
-
-template <typename T>
-int launch_x(bool inv, int nx, const void* src, void* dst, long nrows, const void* twx, hipStream_t st);
-
-template <typename T>
-int launch_y(bool inv, int ny, void* buf, int M, int nz, const void* twy, hipStream_t st);
-
-// mode: Z_STEP (forward, propagate, partials, inverse) or Z_FORWARD (partials only).
-// *nparts receives the number of partial records written when want_inv != 0.
-template <typename T>
-int launch_z(int mode, int nz, void* buf, int M, int ny, long comp_stride, const void* twz, const PropParams& pp,
-             double* partials, int want_inv, hipStream_t st);
+// Geometry of the state: nx reals per row, M = nx/2 complex per row.
+struct Grid3 {
+    int nx, ny, nz, M;
+    long cs() const { return (long)nz * ny * M; }  // complex elements per component
+};
 
 template <typename T>
-int z_partial_count(int nz, int M, int ny);
+int launch_x(bool inv, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st);
 
+// single-component C2C along y or z on each member's work buffer (six components, in place)
 template <typename T>
-int launch_z_fwd_store(int nz, void* buf, int M, int ny, long comp_stride, const void* twz, hipStream_t st);
+int launch_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const void* tw, hipStream_t st);
+
+// fused pass along `axis` on each member's work buffer: mode Z_STEP (forward, propagate,
+// partials, inverse, store) or Z_FORWARD (forward, partials only; memory untouched)
+template <typename T>
+int launch_fused(int mode, int axis, const Grid3& g, const void* md, int nm, const void* tw, int want_inv,
+                 hipStream_t st);
+
+// number of partial records the fused pass writes per member (-1: unsupported length)
+template <typename T>
+int fused_partial_count(int axis, const Grid3& g);
+
+// finalize each member's partials into its invariant record
+template <typename T>
+int launch_finalize(const void* md, int nm, int nparts, hipStream_t st);
 
 }  // namespace eifp

@@ -5,9 +5,9 @@
 
 namespace eifp {
 
-// values per thread for the single-component passes (x, y): radix-16/12 plans
+// values per thread for the single-component passes (x, y, z): radix-16/12 plans
 template <int N> struct XYE { static constexpr int E = (N % 3 == 0) ? (N >= 12 ? 12 : N) : (N >= 16 ? 16 : N); };
-// values per thread for the fused z pass, which holds six components at once: 4 or 6
+// values per thread for the fused pass, which holds six components at once: 4 or 6
 // in FP64, 8 or 12 in FP32 (keeps the six pencils in registers without spilling)
 #ifndef EIFP_ZE64
 #define EIFP_ZE64 4
@@ -28,81 +28,98 @@ template <typename T, int M> struct XCfg {
     using P = Plan<M, XYE<M>::E>;
     static constexpr int NP = cmax(1, cmin(256 / P::T, (48 * 1024) / ((M + 1) * 2 * (int)sizeof(T))));
 };
-template <typename T, int N> struct YCfg {
+
+// Row segment (bytes along x) of a tile of the single-component strided pass.
+#ifndef EIFP_CROW_BYTES
+#define EIFP_CROW_BYTES 256
+#endif
+template <typename T, int N> struct CCfg {
     using P = Plan<N, XYE<N>::E>;
-    static constexpr int B = cmax(1, cmin(cmin(64, 256 / P::T), (64 * 1024) / (N * 2 * (int)sizeof(T))));
+    static constexpr int B0 = cmin(64, cmax(EIFP_CROW_BYTES / (2 * (int)sizeof(T)), 256 / P::T));
+    // at most 1024 threads and ~72 KB of LDS ([pos][col] pitch B + pad, two planes)
+    static constexpr int B =
+        cmax(1, cmin(cmin(B0, 1024 / P::T), (72 * 1024) / (N * 2 * (int)sizeof(T)) - EIFP_LDS_PAD));
 };
-// Row segment (bytes along x) targeted by a z tile; the double-buffered exchange takes
-// 4 N B sizeof(T) bytes of LDS.
+
+// Row segment targeted by a tile of the fused pass; its double-buffered exchange takes
+// 4 N (B + pad) sizeof(T) bytes of LDS.
 #ifndef EIFP_ZROW_BYTES
 #define EIFP_ZROW_BYTES 128
 #endif
 template <typename T, int N> struct ZCfg {
     using P = Plan<N, ZE<T, N>::E>;
-    // row segments of EIFP_ZROW_BYTES along x, at most 1024 threads and 96 KB of LDS
     static constexpr int B0 = cmin(64, cmax(EIFP_ZROW_BYTES / (2 * (int)sizeof(T)), 256 / P::T));
-    static constexpr int B = cmax(1, cmin(cmin(B0, 1024 / P::T), (96 * 1024) / (N * 4 * (int)sizeof(T))));
+    static constexpr int B =
+        cmax(1, cmin(cmin(B0, 1024 / P::T), (96 * 1024) / (N * 4 * (int)sizeof(T)) - EIFP_LDS_PAD));
 };
 
 inline int check_launch() { return hipGetLastError() == hipSuccess ? kOk : kLaunchFailed; }
 
+// axis strides (complex elements): pencil stride, outer stride, outer count
+struct AxisGeom {
+    long pstride, ostride;
+    int n_outer;
+};
+inline AxisGeom axis_geom(int axis, const Grid3& g) {
+    if (axis == AXIS_Y) return {(long)g.M, (long)g.ny * g.M, g.nz};
+    return {(long)g.ny * g.M, (long)g.M, g.ny};
+}
+
 template <typename T, int M>
-int run_x(bool inv, const void* src, void* dst, long nrows, const void* twx, hipStream_t st) {
+int run_x(bool inv, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st) {
     using C = XCfg<T, M>;
-    const dim3 grid((unsigned)((nrows + C::NP - 1) / C::NP));
+    const long nrows = 6L * g.nz * g.ny;
+    const dim3 grid((unsigned)((nrows + C::NP - 1) / C::NP), (unsigned)nm);
     const dim3 block(C::P::T * C::NP);
+    const MemberDesc<T>* d = (const MemberDesc<T>*)md;
     if (inv)
-        hipLaunchKernelGGL((k_x_inv<T, typename C::P, C::NP>), grid, block, 0, st, (const cpx<T>*)src, (cpx<T>*)dst,
-                           nrows, (const cpx<T>*)twx);
+        hipLaunchKernelGGL((k_x_inv<T, typename C::P, C::NP>), grid, block, 0, st, d, nrows, (const cpx<T>*)twx);
     else
-        hipLaunchKernelGGL((k_x_fwd<T, typename C::P, C::NP>), grid, block, 0, st, (const cpx<T>*)src, (cpx<T>*)dst,
-                           nrows, (const cpx<T>*)twx);
+        hipLaunchKernelGGL((k_x_fwd<T, typename C::P, C::NP>), grid, block, 0, st, d, nrows, (const cpx<T>*)twx);
     return check_launch();
 }
 
 template <typename T, int N>
-int run_y(bool inv, void* buf, int M, int nz, const void* twy, hipStream_t st) {
-    using C = YCfg<T, N>;
-    const dim3 grid((unsigned)((M + C::B - 1) / C::B), (unsigned)nz, 6);
+int run_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const void* tw, hipStream_t st) {
+    using C = CCfg<T, N>;
+    const AxisGeom a = axis_geom(axis, g);
+    const dim3 grid((unsigned)((g.M + C::B - 1) / C::B), (unsigned)a.n_outer, (unsigned)(6 * nm));
     const dim3 block(C::P::T * C::B);
+    const MemberDesc<T>* d = (const MemberDesc<T>*)md;
     if (inv)
-        hipLaunchKernelGGL((k_y<T, typename C::P, C::B, true>), grid, block, 0, st, (cpx<T>*)buf, M, nz,
-                           (const cpx<T>*)twy);
+        hipLaunchKernelGGL((k_c2c<T, typename C::P, C::B, true>), grid, block, 0, st, d, g.M, a.pstride, a.ostride,
+                           g.cs(), (const cpx<T>*)tw);
     else
-        hipLaunchKernelGGL((k_y<T, typename C::P, C::B, false>), grid, block, 0, st, (cpx<T>*)buf, M, nz,
-                           (const cpx<T>*)twy);
+        hipLaunchKernelGGL((k_c2c<T, typename C::P, C::B, false>), grid, block, 0, st, d, g.M, a.pstride, a.ostride,
+                           g.cs(), (const cpx<T>*)tw);
     return check_launch();
 }
 
-template <typename T, int N>
-int run_z(int mode, void* buf, int M, int ny, long cs, const void* twz, const PropParams& pp, double* partials,
-          int want_inv, hipStream_t st) {
+template <typename T, int N, int MODE, int AXIS>
+void run_fused_k(const Grid3& g, const void* md, int nm, const void* tw, int want_inv, hipStream_t st) {
     using C = ZCfg<T, N>;
-    const dim3 grid((unsigned)((M + C::B - 1) / C::B), (unsigned)ny);
+    const AxisGeom a = axis_geom(AXIS, g);
+    const dim3 grid((unsigned)((g.M + C::B - 1) / C::B), (unsigned)a.n_outer, (unsigned)nm);
     const dim3 block(C::P::T * C::B);
-    if (mode == Z_STEP)
-        hipLaunchKernelGGL((k_z<T, typename C::P, C::B, Z_STEP>), grid, block, 0, st, (cpx<T>*)buf, M, ny, cs,
-                           (const cpx<T>*)twz, pp, partials, want_inv);
-    else
-        hipLaunchKernelGGL((k_z<T, typename C::P, C::B, Z_FORWARD>), grid, block, 0, st, (cpx<T>*)buf, M, ny, cs,
-                           (const cpx<T>*)twz, pp, partials, want_inv);
+    hipLaunchKernelGGL((k_fused<T, typename C::P, C::B, MODE, AXIS>), grid, block, 0, st, (const MemberDesc<T>*)md,
+                       g.M, a.n_outer, a.pstride, a.ostride, g.cs(), (const cpx<T>*)tw, want_inv);
+}
+
+template <typename T, int N>
+int run_fused(int mode, int axis, const Grid3& g, const void* md, int nm, const void* tw, int want_inv,
+              hipStream_t st) {
+    // only the y-fused form is compiled (the step's pass order); the kernel template
+    // also covers z-fused pencils
+    if (axis != AXIS_Y) return kUnsupported;
+    if (mode == Z_STEP) run_fused_k<T, N, Z_STEP, AXIS_Y>(g, md, nm, tw, want_inv, st);
+    else run_fused_k<T, N, Z_FORWARD, AXIS_Y>(g, md, nm, tw, want_inv, st);
     return check_launch();
 }
 
 template <typename T, int N>
-int count_z(int M, int ny) {
+int count_fused(int axis, const Grid3& g) {
     using C = ZCfg<T, N>;
-    return ((M + C::B - 1) / C::B) * ny;
-}
-
-template <typename T, int N>
-int run_z_store(void* buf, int M, int ny, long cs, const void* twz, hipStream_t st) {
-    using C = ZCfg<T, N>;
-    const dim3 grid((unsigned)((M + C::B - 1) / C::B), (unsigned)ny, 6);
-    const dim3 block(C::P::T * C::B);
-    hipLaunchKernelGGL((k_z_fwd_store<T, typename C::P, C::B>), grid, block, 0, st, (cpx<T>*)buf, M, ny, cs,
-                       (const cpx<T>*)twz);
-    return check_launch();
+    return ((g.M + C::B - 1) / C::B) * axis_geom(axis, g).n_outer;
 }
 
 // axis lengths compiled for y and z
@@ -110,12 +127,14 @@ int run_z_store(void* buf, int M, int ny, long cs, const void* twz, hipStream_t 
 // half lengths M = Nx/2 compiled for x
 #define EIFP_HALF_SIZES(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
 
+inline int axis_len(int axis, const Grid3& g) { return axis == AXIS_Y ? g.ny : g.nz; }
+
 template <typename T>
-int launch_x(bool inv, int nx, const void* src, void* dst, long nrows, const void* twx, hipStream_t st) {
-    switch (nx / 2) {
-#define EIFP_CASE(M) \
-    case M:          \
-        return run_x<T, M>(inv, src, dst, nrows, twx, st);
+int launch_x(bool inv, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st) {
+    switch (g.M) {
+#define EIFP_CASE(MM) \
+    case MM:          \
+        return run_x<T, MM>(inv, g, md, nm, twx, st);
         EIFP_HALF_SIZES(EIFP_CASE)
 #undef EIFP_CASE
         default:
@@ -124,11 +143,11 @@ int launch_x(bool inv, int nx, const void* src, void* dst, long nrows, const voi
 }
 
 template <typename T>
-int launch_y(bool inv, int ny, void* buf, int M, int nz, const void* twy, hipStream_t st) {
-    switch (ny) {
+int launch_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const void* tw, hipStream_t st) {
+    switch (axis_len(axis, g)) {
 #define EIFP_CASE(N) \
     case N:          \
-        return run_y<T, N>(inv, buf, M, nz, twy, st);
+        return run_c2c<T, N>(inv, axis, g, md, nm, tw, st);
         EIFP_AXIS_SIZES(EIFP_CASE)
 #undef EIFP_CASE
         default:
@@ -137,12 +156,12 @@ int launch_y(bool inv, int ny, void* buf, int M, int nz, const void* twy, hipStr
 }
 
 template <typename T>
-int launch_z(int mode, int nz, void* buf, int M, int ny, long cs, const void* twz, const PropParams& pp,
-             double* partials, int want_inv, hipStream_t st) {
-    switch (nz) {
+int launch_fused(int mode, int axis, const Grid3& g, const void* md, int nm, const void* tw, int want_inv,
+                 hipStream_t st) {
+    switch (axis_len(axis, g)) {
 #define EIFP_CASE(N) \
     case N:          \
-        return run_z<T, N>(mode, buf, M, ny, cs, twz, pp, partials, want_inv, st);
+        return run_fused<T, N>(mode, axis, g, md, nm, tw, want_inv, st);
         EIFP_AXIS_SIZES(EIFP_CASE)
 #undef EIFP_CASE
         default:
@@ -151,11 +170,11 @@ int launch_z(int mode, int nz, void* buf, int M, int ny, long cs, const void* tw
 }
 
 template <typename T>
-int z_partial_count(int nz, int M, int ny) {
-    switch (nz) {
+int fused_partial_count(int axis, const Grid3& g) {
+    switch (axis_len(axis, g)) {
 #define EIFP_CASE(N) \
     case N:          \
-        return count_z<T, N>(M, ny);
+        return count_fused<T, N>(axis, g);
         EIFP_AXIS_SIZES(EIFP_CASE)
 #undef EIFP_CASE
         default:
@@ -164,24 +183,16 @@ int z_partial_count(int nz, int M, int ny) {
 }
 
 template <typename T>
-int launch_z_fwd_store(int nz, void* buf, int M, int ny, long cs, const void* twz, hipStream_t st) {
-    switch (nz) {
-#define EIFP_CASE(N) \
-    case N:          \
-        return run_z_store<T, N>(buf, M, ny, cs, twz, st);
-        EIFP_AXIS_SIZES(EIFP_CASE)
-#undef EIFP_CASE
-        default:
-            return kUnsupported;
-    }
+int launch_finalize(const void* md, int nm, int nparts, hipStream_t st) {
+    hipLaunchKernelGGL((k_finalize<T>), dim3(nm), dim3(1024), 0, st, (const MemberDesc<T>*)md, nparts);
+    return check_launch();
 }
 
 #define EIFP_INSTANTIATE(T)                                                                                   \
-    template int launch_x<T>(bool, int, const void*, void*, long, const void*, hipStream_t);                  \
-    template int launch_y<T>(bool, int, void*, int, int, const void*, hipStream_t);                           \
-    template int launch_z<T>(int, int, void*, int, int, long, const void*, const PropParams&, double*, int,    \
-                             hipStream_t);                                                                    \
-    template int z_partial_count<T>(int, int, int);                                                           \
-    template int launch_z_fwd_store<T>(int, void*, int, int, long, const void*, hipStream_t);
+    template int launch_x<T>(bool, const Grid3&, const void*, int, const void*, hipStream_t);                 \
+    template int launch_c2c<T>(bool, int, const Grid3&, const void*, int, const void*, hipStream_t);          \
+    template int launch_fused<T>(int, int, const Grid3&, const void*, int, const void*, int, hipStream_t);    \
+    template int fused_partial_count<T>(int, const Grid3&);                                                   \
+    template int launch_finalize<T>(const void*, int, int, hipStream_t);
 
 }  // namespace eifp

@@ -28,7 +28,7 @@ EIFP_FP64 = 0
 EIFP_FP32 = 1
 PRECISIONS = {"fp64": EIFP_FP64, "fp32": EIFP_FP32}
 
-PASS_NAMES = ("x_fwd", "y_fwd", "z_fused", "y_inv", "x_inv", "finalize")
+PASS_NAMES = ("x_fwd", "z_fwd", "y_fused", "z_inv", "x_inv", "finalize")
 
 
 class eifp_domain(ctypes.Structure):
