@@ -135,6 +135,125 @@ const char *eifp_status_string(eifp_status st);
 /* Detail of the last failure on the calling thread ("" if none). */
 const char *eifp_last_error(void);
 
+/* ===================================================================================
+ * Serving: a persistent loop that runs many independent solves of the scheme above
+ * (each one an init + step(tau, nsteps) with invariants every `cadence` steps) as they
+ * arrive.  Same-shape, same-precision solves share every kernel launch (a batch of
+ * "members"); solves of different shapes run on separate streams and overlap on the
+ * device.  Requests are admitted in arrival order as their device footprint fits the
+ * memory budget and the batch has a free slot; new ones join a batch between chunks
+ * of steps, so a request never waits for the whole batch to finish.  Each member's
+ * arithmetic is independent of the others in its batch: a solve gives the same bits
+ * alone and in any mix.
+ *
+ * Threading: every server call may be made from any host thread; one internal thread
+ * drives the GPU.
+ * =================================================================================== */
+typedef struct eifp_server eifp_server; /* opaque, owned by the library */
+
+enum {
+    EIFP_SERVER_DRY_RUN = 1,  /* schedule only: no device memory, no kernels (host tests) */
+    EIFP_SERVER_NO_GRAPHS = 2,/* launch kernels one by one instead of replaying a captured
+                                 HIP graph per (shape, batch size) */
+    EIFP_SERVER_SERIAL = 4    /* at most one solve on the device at a time (baseline) */
+};
+
+enum {
+    EIFP_REQ_KEEP_RESULT = 1, /* keep the final fields on the device after completion,
+                                 for eifp_server_fields, until eifp_server_release */
+    EIFP_REQ_NO_SNAPSHOT = 2  /* no device-side field snapshot at each output */
+};
+
+/* One solve (Alg. 2 on Omega = dom with constants mu, eps, step tau, nsteps steps). */
+typedef struct {
+    int nx, ny, nz;             /* as eifp_init */
+    eifp_domain dom;
+    double mu, eps, tau;        /* tau finite, may be negative */
+    long long nsteps;           /* >= 1 */
+    long long cadence;          /* an output event every `cadence` steps; 0: only at the end */
+    eifp_precision prec;
+    const double *H0, *E0;      /* host, 3*nx*ny*nz doubles each, [3][nz][ny][nx]; copied by submit */
+    unsigned long long user_tag;/* returned in every event of this request */
+    int flags;                  /* EIFP_REQ_* */
+} eifp_request;
+
+typedef enum {
+    EIFP_EV_OUTPUT = 0, /* cadence point reached: invariants after `step` steps */
+    EIFP_EV_DONE = 1,   /* all steps done: final invariants */
+    EIFP_EV_ERROR = 2   /* the request failed (status says why) and was dropped */
+} eifp_event_kind;
+
+typedef struct {
+    unsigned long long user_tag;
+    long long req_id;
+    int kind;                   /* eifp_event_kind */
+    eifp_status status;
+    long long step;             /* steps done when the event was produced */
+    eifp_invariant_set inv;     /* invariants of the state after `step` steps */
+    double t_arrive;            /* seconds on the server's clock: submit */
+    double t_admit;             /* admission (device memory allocated, upload enqueued) */
+    double t_event;             /* the event was observed complete on the host */
+} eifp_event;
+
+typedef struct {
+    long long submitted, admitted, completed, failed;
+    long long queued, running;  /* now */
+    long long peak_running;     /* most requests admitted at once */
+    double p50_s, p99_s, mean_s, max_s; /* latency = completion - arrival, completed requests */
+    double point_steps;         /* sum over completed requests of nx*ny*nz*nsteps */
+    double wall_s;              /* first arrival -> last completion */
+    double point_steps_per_s;   /* point_steps / wall_s */
+    long long bytes_in_use, peak_bytes, budget_bytes;
+    long long chunks;           /* batched chunk launches */
+    double mean_batch;          /* members per chunk, averaged over chunks */
+} eifp_server_stat_set;
+
+/* Create a server.
+ *   hbm_budget_bytes  device memory the server may hold for solves (footprints below
+ *                     plus per-batch tables); requests wait until theirs fits
+ *   max_batch         members per batch (1..1024)
+ *   flags             EIFP_SERVER_*
+ * Errors: INVALID_ARG, DEVICE (stream or thread creation failed). */
+eifp_status eifp_server_create(eifp_server **out, long long hbm_budget_bytes, int max_batch, int flags);
+
+/* Device bytes one request of this shape holds while admitted: its state, plus an equal
+ * snapshot buffer unless EIFP_REQ_NO_SNAPSHOT.  0 for an invalid shape or precision. */
+long long eifp_server_footprint(int nx, int ny, int nz, eifp_precision prec, int flags);
+
+/* Queue a solve; the fields are copied before returning.  *req_id receives its id.
+ * Errors: INVALID_ARG (as eifp_init, plus nsteps < 1, cadence < 0), UNSUPPORTED_SIZE,
+ * NONFINITE, OUT_OF_MEMORY (the footprint alone exceeds the budget), STATE (server
+ * shutting down). */
+eifp_status eifp_server_submit(eifp_server *sv, const eifp_request *rq, long long *req_id);
+
+/* Take up to max_events events (oldest first) into ev; *n_events receives the count.
+ * Waits up to wait_ms milliseconds for the first one (0: do not wait, < 0: wait until
+ * one arrives or the server has no queued or running request).  Errors: INVALID_ARG. */
+eifp_status eifp_server_poll(eifp_server *sv, eifp_event *ev, int max_events, int *n_events, int wait_ms);
+
+/* Copy a request's fields to host arrays as eifp_fields: for a running request, its
+ * latest snapshot (taken at an output point; it may be newer than the last event
+ * polled); for a finished request kept with EIFP_REQ_KEEP_RESULT, its final state.
+ * *step (if not NULL) receives the step count of the copied fields.  Blocks until the
+ * copy is done.  Errors: INVALID_ARG (unknown id, NULL), STATE (no snapshot yet,
+ * snapshots disabled, result not kept or released), DEVICE. */
+eifp_status eifp_server_fields(eifp_server *sv, long long req_id, double *H, double *E, long long *step);
+
+/* Free the device memory of a finished request kept with EIFP_REQ_KEEP_RESULT.
+ * Errors: INVALID_ARG (unknown id), STATE (not finished or not kept). */
+eifp_status eifp_server_release(eifp_server *sv, long long req_id);
+
+/* Counters and latency percentiles so far. */
+eifp_status eifp_server_stats(eifp_server *sv, eifp_server_stat_set *out);
+
+/* Block until no request is queued or running (or timeout_ms passes, if >= 0; then
+ * STATE).  Errors: INVALID_ARG, STATE, DEVICE. */
+eifp_status eifp_server_drain(eifp_server *sv, int timeout_ms);
+
+/* Stop the loop, drop queued requests, wait for running chunks, free everything.
+ * NULL is accepted. */
+eifp_status eifp_server_destroy(eifp_server *sv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -47,6 +47,53 @@ class eifp_invariant_set(ctypes.Structure):
     ]
 
 
+EIFP_SERVER_DRY_RUN = 1
+EIFP_SERVER_NO_GRAPHS = 2
+EIFP_SERVER_SERIAL = 4
+EIFP_REQ_KEEP_RESULT = 1
+EIFP_REQ_NO_SNAPSHOT = 2
+EIFP_EV_OUTPUT = 0
+EIFP_EV_DONE = 1
+EIFP_EV_ERROR = 2
+EVENT_KINDS = {EIFP_EV_OUTPUT: "output", EIFP_EV_DONE: "done", EIFP_EV_ERROR: "error"}
+
+
+class eifp_request(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("dom", eifp_domain),
+        ("mu", ctypes.c_double), ("eps", ctypes.c_double), ("tau", ctypes.c_double),
+        ("nsteps", ctypes.c_longlong), ("cadence", ctypes.c_longlong),
+        ("prec", ctypes.c_int),
+        ("H0", ctypes.POINTER(ctypes.c_double)), ("E0", ctypes.POINTER(ctypes.c_double)),
+        ("user_tag", ctypes.c_ulonglong),
+        ("flags", ctypes.c_int),
+    ]
+
+
+class eifp_event(ctypes.Structure):
+    _fields_ = [
+        ("user_tag", ctypes.c_ulonglong),
+        ("req_id", ctypes.c_longlong),
+        ("kind", ctypes.c_int),
+        ("status", ctypes.c_int),
+        ("step", ctypes.c_longlong),
+        ("inv", eifp_invariant_set),
+        ("t_arrive", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_event", ctypes.c_double),
+    ]
+
+
+class eifp_server_stat_set(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_longlong) for n in
+                ("submitted", "admitted", "completed", "failed", "queued", "running", "peak_running")] + \
+               [(n, ctypes.c_double) for n in ("p50_s", "p99_s", "mean_s", "max_s", "point_steps", "wall_s",
+                                                "point_steps_per_s")] + \
+               [(n, ctypes.c_longlong) for n in ("bytes_in_use", "peak_bytes", "budget_bytes", "chunks")] + \
+               [("mean_batch", ctypes.c_double)]
+
+
 # every symbol the header declares, with (restype, argtypes)
 _VP = ctypes.c_void_p
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -66,6 +113,17 @@ SIGNATURES = {
     "eifp_destroy": (ctypes.c_int, [_VP]),
     "eifp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "eifp_last_error": (ctypes.c_char_p, []),
+    "eifp_server_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_longlong, ctypes.c_int, ctypes.c_int]),
+    "eifp_server_footprint": (ctypes.c_longlong, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                  ctypes.c_int]),
+    "eifp_server_submit": (ctypes.c_int, [_VP, ctypes.POINTER(eifp_request), ctypes.POINTER(ctypes.c_longlong)]),
+    "eifp_server_poll": (ctypes.c_int, [_VP, ctypes.POINTER(eifp_event), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+    "eifp_server_fields": (ctypes.c_int, [_VP, ctypes.c_longlong, _DP, _DP, ctypes.POINTER(ctypes.c_longlong)]),
+    "eifp_server_release": (ctypes.c_int, [_VP, ctypes.c_longlong]),
+    "eifp_server_stats": (ctypes.c_int, [_VP, ctypes.POINTER(eifp_server_stat_set)]),
+    "eifp_server_drain": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "eifp_server_destroy": (ctypes.c_int, [_VP]),
 }
 
 _lib = None
@@ -151,11 +209,15 @@ def eifp_step_timed(handle, tau, nsteps=1) -> dict:
     return dict(zip(PASS_NAMES, out.tolist()))
 
 
+def _inv_dict(inv: eifp_invariant_set) -> dict:
+    return {"t": inv.t, "steps_done": inv.steps_done, "energy": inv.energy, "helicity": inv.helicity,
+            "momentum": list(inv.momentum), "div_h_l2": inv.div_h_l2, "div_e_l2": inv.div_e_l2}
+
+
 def eifp_invariants(handle) -> dict:
     inv = eifp_invariant_set()
     _check(load().eifp_invariants(handle, ctypes.byref(inv)), "eifp_invariants")
-    return {"t": inv.t, "steps_done": inv.steps_done, "energy": inv.energy, "helicity": inv.helicity,
-            "momentum": list(inv.momentum), "div_h_l2": inv.div_h_l2, "div_e_l2": inv.div_e_l2}
+    return _inv_dict(inv)
 
 
 def eifp_fields(handle, shape):
@@ -240,6 +302,120 @@ class Solver:
     def close(self):
         if self.handle:
             eifp_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------------
+# serving
+# ----------------------------------------------------------------------------------
+
+def eifp_server_create(budget_bytes, max_batch=32, flags=0) -> int:
+    h = _VP()
+    _check(load().eifp_server_create(ctypes.byref(h), int(budget_bytes), int(max_batch), int(flags)),
+           "eifp_server_create")
+    return h.value
+
+
+def eifp_server_footprint(nx, ny, nz, prec, flags=0) -> int:
+    p = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    return int(load().eifp_server_footprint(nx, ny, nz, p, int(flags)))
+
+
+def eifp_server_submit(handle, H0, E0, domain, mu, eps, tau, nsteps, cadence=0, prec="fp64", tag=0,
+                       flags=0) -> int:
+    H0 = _field(H0)
+    _, nz, ny, nx = H0.shape
+    E0 = _field(E0, H0.shape)
+    p = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    rq = eifp_request(nx, ny, nz, eifp_domain(*[float(v) for v in domain]), float(mu), float(eps), float(tau),
+                      int(nsteps), int(cadence), p, _dp(H0), _dp(E0), int(tag), int(flags))
+    rid = ctypes.c_longlong()
+    _check(load().eifp_server_submit(handle, ctypes.byref(rq), ctypes.byref(rid)), "eifp_server_submit")
+    return rid.value
+
+
+def eifp_server_poll(handle, max_events=256, wait_ms=0) -> list:
+    buf = (eifp_event * max(1, max_events))()
+    n = ctypes.c_int()
+    _check(load().eifp_server_poll(handle, buf, int(max_events), ctypes.byref(n), int(wait_ms)),
+           "eifp_server_poll")
+    out = []
+    for e in buf[:n.value]:
+        out.append({"tag": e.user_tag, "req_id": e.req_id, "kind": EVENT_KINDS.get(e.kind, e.kind),
+                    "status": e.status, "step": e.step, "inv": _inv_dict(e.inv), "t_arrive": e.t_arrive,
+                    "t_admit": e.t_admit, "t_event": e.t_event})
+    return out
+
+
+def eifp_server_fields(handle, req_id, shape):
+    """Returns (H, E, step): the fields of a request and the step count they are at."""
+    nx, ny, nz = shape
+    H = np.empty((3, nz, ny, nx))
+    E = np.empty((3, nz, ny, nx))
+    step = ctypes.c_longlong()
+    _check(load().eifp_server_fields(handle, int(req_id), _dp(H), _dp(E), ctypes.byref(step)),
+           "eifp_server_fields")
+    return H, E, step.value
+
+
+def eifp_server_release(handle, req_id):
+    _check(load().eifp_server_release(handle, int(req_id)), "eifp_server_release")
+
+
+def eifp_server_stats(handle) -> dict:
+    s = eifp_server_stat_set()
+    _check(load().eifp_server_stats(handle, ctypes.byref(s)), "eifp_server_stats")
+    return {name: getattr(s, name) for name, _ in s._fields_}
+
+
+def eifp_server_drain(handle, timeout_ms=-1):
+    _check(load().eifp_server_drain(handle, int(timeout_ms)), "eifp_server_drain")
+
+
+def eifp_server_destroy(handle):
+    _check(load().eifp_server_destroy(handle), "eifp_server_destroy")
+
+
+class Server:
+    """Owns one library server.  ``Server(budget_bytes, max_batch=32, flags=0)``."""
+
+    def __init__(self, budget_bytes, max_batch=32, flags=0):
+        self.handle = eifp_server_create(budget_bytes, max_batch, flags)
+
+    def submit(self, H0, E0, domain, mu=1.0, eps=1.0, tau=0.1, nsteps=1, cadence=0, prec="fp64", tag=0,
+               flags=0) -> int:
+        return eifp_server_submit(self.handle, H0, E0, domain, mu, eps, tau, nsteps, cadence, prec, tag, flags)
+
+    def poll(self, max_events=256, wait_ms=0) -> list:
+        return eifp_server_poll(self.handle, max_events, wait_ms)
+
+    def fields(self, req_id, shape):
+        return eifp_server_fields(self.handle, req_id, shape)
+
+    def release(self, req_id):
+        eifp_server_release(self.handle, req_id)
+
+    def stats(self) -> dict:
+        return eifp_server_stats(self.handle)
+
+    def drain(self, timeout_ms=-1):
+        eifp_server_drain(self.handle, timeout_ms)
+
+    def close(self):
+        if self.handle:
+            eifp_server_destroy(self.handle)
             self.handle = 0
 
     def __enter__(self):

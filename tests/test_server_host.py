@@ -1,0 +1,188 @@
+"""Host logic of the serving loop, run without a GPU: the server's dry-run mode schedules
+requests (admission by device footprint, batching by shape, chunking at output points,
+events, statistics) exactly as the device mode does but allocates and launches nothing."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2210_06232_amd", "libeifp.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libeifp.so not built")
+
+CUBE = (0.0, 2 * math.pi, 0.0, 2 * math.pi, 0.0, 2 * math.pi)
+
+
+def eifp():
+    from paper_2210_06232_amd import eifp as m
+    return m
+
+
+def zeros(n):
+    return np.zeros((3, n, n, n))
+
+
+def events_by_request(evs):
+    out = {}
+    for e in evs:
+        out.setdefault(e["req_id"], []).append(e)
+    return out
+
+
+def drain_events(sv):
+    sv.drain(20000)
+    evs = []
+    while True:
+        got = sv.poll(4096, 0)
+        if not got:
+            return evs
+        evs += got
+
+
+def test_footprint():
+    m = eifp()
+    assert m.eifp_server_footprint(32, 32, 32, "fp64") == 2 * 6 * 32 ** 3 * 8
+    assert m.eifp_server_footprint(32, 32, 32, "fp32") == 2 * 6 * 32 ** 3 * 4
+    assert m.eifp_server_footprint(32, 32, 32, "fp64", m.EIFP_REQ_NO_SNAPSHOT) == 6 * 32 ** 3 * 8
+    assert m.eifp_server_footprint(64, 128, 256, "fp32") == 2 * 6 * 64 * 128 * 256 * 4
+    assert m.eifp_server_footprint(31, 32, 32, "fp64") == 0
+    assert m.eifp_server_footprint(32, 32, 32, 7) == 0
+
+
+def test_events_follow_the_cadence():
+    m = eifp()
+    with m.Server(1 << 30, 8, m.EIFP_SERVER_DRY_RUN) as sv:
+        cases = [(8, 25, 10), (8, 30, 10), (16, 7, 0), (8, 1, 1), (16, 100, 7), (12, 5, 50)]
+        ids = {}
+        for tag, (n, nsteps, cad) in enumerate(cases):
+            ids[sv.submit(zeros(n), zeros(n), CUBE, tau=0.1, nsteps=nsteps, cadence=cad, tag=tag)] = (tag, nsteps, cad)
+        evs = events_by_request(drain_events(sv))
+        assert set(evs) == set(ids)
+        for rid, (tag, nsteps, cad) in ids.items():
+            got = evs[rid]
+            assert all(e["tag"] == tag for e in got)
+            want = [s for s in range(cad, nsteps, cad)] if cad else []
+            assert [e["step"] for e in got if e["kind"] == "output"] == want
+            assert [e["kind"] for e in got][-1] == "done" and got[-1]["step"] == nsteps
+            assert sum(e["kind"] == "done" for e in got) == 1
+            assert all(e["status"] == 0 for e in got)
+            assert all(abs(e["inv"]["t"] - 0.1 * e["step"]) < 1e-12 for e in got)
+            assert all(e["t_arrive"] <= e["t_admit"] <= e["t_event"] for e in got)
+        st = sv.stats()
+        assert st["completed"] == len(cases) and st["failed"] == 0
+        assert st["queued"] == 0 and st["running"] == 0
+        assert st["point_steps"] == sum(n ** 3 * ns for n, ns, _ in cases)
+        assert 0 <= st["p50_s"] <= st["p99_s"] <= st["max_s"]
+        assert st["chunks"] >= 1 and st["mean_batch"] >= 1
+
+
+def test_admission_respects_the_budget():
+    m = eifp()
+    fp = m.eifp_server_footprint(32, 32, 32, "fp64")
+    # room for two requests plus the batch tables of one shape, not three requests
+    budget = int(2.5 * fp)
+    with m.Server(budget, 4, m.EIFP_SERVER_DRY_RUN) as sv:
+        for i in range(12):
+            sv.submit(zeros(32), zeros(32), CUBE, nsteps=2000, cadence=100, tag=i)
+        evs = drain_events(sv)
+        st = sv.stats()
+    assert st["completed"] == 12
+    assert st["peak_bytes"] <= budget
+    assert st["peak_running"] <= 2
+    assert sum(e["kind"] == "done" for e in evs) == 12
+
+
+def test_serial_mode_runs_one_request_at_a_time():
+    m = eifp()
+    with m.Server(1 << 34, 16, m.EIFP_SERVER_DRY_RUN | m.EIFP_SERVER_SERIAL) as sv:
+        for i in range(10):
+            n = (8, 16, 32)[i % 3]
+            sv.submit(zeros(n), zeros(n), CUBE, nsteps=50 + i, cadence=10, tag=i)
+        evs = drain_events(sv)
+        st = sv.stats()
+    assert st["completed"] == 10 and st["peak_running"] == 1 and st["mean_batch"] == 1.0
+    # one at a time, in arrival order
+    done = [e["tag"] for e in evs if e["kind"] == "done"]
+    assert done == list(range(10))
+
+
+def test_submit_validation():
+    m = eifp()
+    z = zeros(8)
+    bad = z.copy()
+    bad[2, 1, 1, 1] = np.nan
+    with m.Server(1 << 30, 4, m.EIFP_SERVER_DRY_RUN) as sv:
+        cases = [
+            (dict(H0=np.zeros((3, 8, 8, 7)), E0=np.zeros((3, 8, 8, 7))), m.EIFP_ERR_INVALID_ARG),
+            (dict(H0=np.zeros((3, 8, 8, 10)), E0=np.zeros((3, 8, 8, 10))), m.EIFP_ERR_UNSUPPORTED_SIZE),
+            (dict(nsteps=0), m.EIFP_ERR_INVALID_ARG),
+            (dict(cadence=-1), m.EIFP_ERR_INVALID_ARG),
+            (dict(tau=float("inf")), m.EIFP_ERR_INVALID_ARG),
+            (dict(mu=0.0), m.EIFP_ERR_INVALID_ARG),
+            (dict(domain=(0, 1, 1, 1, 0, 1)), m.EIFP_ERR_INVALID_ARG),
+            (dict(H0=bad), m.EIFP_ERR_NONFINITE),
+            (dict(prec=5), m.EIFP_ERR_INVALID_ARG),
+        ]
+        for kw, want in cases:
+            args = dict(H0=z, E0=z, domain=CUBE, nsteps=10, cadence=0)
+            args.update(kw)
+            with pytest.raises(m.EifpError) as ei:
+                sv.submit(**args)
+            assert ei.value.status == want, kw
+        with pytest.raises(m.EifpError) as ei:
+            sv.fields(12345, (8, 8, 8))
+        assert ei.value.status == m.EIFP_ERR_INVALID_ARG
+        assert sv.stats()["submitted"] == 0
+    # a footprint above the whole budget is refused at submit
+    with m.Server(1000, 4, m.EIFP_SERVER_DRY_RUN) as sv:
+        with pytest.raises(m.EifpError) as ei:
+            sv.submit(z, z, CUBE, nsteps=10)
+        assert ei.value.status == m.EIFP_ERR_OUT_OF_MEMORY
+
+
+def test_create_validation_and_poll_without_work():
+    m = eifp()
+    with pytest.raises(m.EifpError):
+        m.Server(0, 4, m.EIFP_SERVER_DRY_RUN)
+    with pytest.raises(m.EifpError):
+        m.Server(1 << 20, 0, m.EIFP_SERVER_DRY_RUN)
+    with m.Server(1 << 20, 4, m.EIFP_SERVER_DRY_RUN) as sv:
+        assert sv.poll(16, 0) == []
+        assert sv.poll(16, -1) == []  # nothing queued or running: returns at once
+        sv.drain(1000)
+
+
+def test_kept_results_hold_memory_until_released():
+    m = eifp()
+    fp = m.eifp_server_footprint(16, 16, 16, "fp32")
+    with m.Server(1 << 30, 4, m.EIFP_SERVER_DRY_RUN) as sv:
+        rid = sv.submit(zeros(16), zeros(16), CUBE, nsteps=20, cadence=5, prec="fp32", flags=m.EIFP_REQ_KEEP_RESULT)
+        drain_events(sv)
+        # the snapshot half of the footprint is returned at completion; the state stays
+        held = sv.stats()["bytes_in_use"]
+        assert held >= fp // 2
+        with pytest.raises(m.EifpError) as ei:
+            sv.fields(rid, (16, 16, 16))  # dry run holds no data
+        assert ei.value.status == m.EIFP_ERR_STATE
+        sv.release(rid)
+        assert sv.stats()["bytes_in_use"] == held - fp // 2
+        with pytest.raises(m.EifpError):
+            sv.release(rid)
+
+
+def test_mixed_stream_batches_same_shapes():
+    m = eifp()
+    rng = np.random.default_rng(3)
+    with m.Server(1 << 36, 32, m.EIFP_SERVER_DRY_RUN) as sv:
+        shapes = [8, 12, 16]
+        n_req = 60
+        for i in range(n_req):
+            n = shapes[rng.integers(3)]
+            sv.submit(zeros(n), zeros(n), CUBE, nsteps=int(rng.integers(10, 3000)), cadence=int(rng.integers(10, 500)),
+                      prec=("fp32", "fp64")[i % 2], tag=i)
+        evs = drain_events(sv)
+        st = sv.stats()
+    assert st["completed"] == n_req and st["failed"] == 0
+    assert sum(e["kind"] == "done" for e in evs) == n_req
+    assert st["bytes_in_use"] >= 0
