@@ -1,23 +1,27 @@
 #!/usr/bin/env python3
-"""Benchmark of the EI-FP time step on one MI355X.
+"""Benchmark of the EI-FP time step on one MI355X, and of the serving loop.
 
 A step is one pass of the whole hot path over the state: forward 3-D FFT of the six
-field components (x R2C, y, z), the exact mode-wise propagator, the invariant partial
-sums, the inverse FFT (z, y, x C2R) and the deterministic invariant finalize.
+field components (x R2C, z, y), the exact mode-wise propagator, the invariant partial
+sums, the inverse FFT (y, z, x C2R) and the deterministic invariant finalize.
 
 Workload: 256^3 grid on [0,2pi] x [0,4pi] x [0,2pi], mu = eps = 1, tau = 0.1, seeded
 random divergence-free fields with spectrum (1+|k|^2)^-2 cut at |k| <= 42.67.  Fields
 are uploaded before the timed region (the state is resident in HBM).
 
+Serving: a seeded stream of mixed-size solves (7 grids from 32^3 to 256^3, 70% FP32,
+log-uniform step counts on [10, 5000]) replayed against the batching server, once with
+Poisson arrivals at 0.8 of one-at-a-time capacity (latency) and once with every
+request arriving at once (throughput), each beside serial FP64 solves of the same
+stream.
+
 Prints ONE JSON line.  ``value`` is FP64 field-point-steps/s; the FP32 form is timed on
-the same input and reported under ``"fp32"``.
+the same input and reported under ``"fp32"``; serving under ``"serving"``.
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -25,27 +29,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2210_06232_amd.profiling import kernel_source_hash  # noqa: E402
+from paper_2210_06232_amd.workload import HEADLINE as WORKLOAD, headline_inputs  # noqa: E402
+
 PEAK_HBM_GBS = 8000.0
-WORKLOAD = {
-    "workload": "eifp-maxwell-256^3-box[2pi,4pi,2pi]-mu1-eps1-tau0.1",
-    "grid": [256, 256, 256],
-    "domain": [0.0, 2 * math.pi, 0.0, 4 * math.pi, 0.0, 2 * math.pi],
-    "mu": 1.0, "eps": 1.0, "tau": 0.1,
-    "spectrum": "(1+|k|^2)^-2, 0<|k|<=42.67, transverse, seeded",
-}
 PASSES = ("x_fwd", "z_fwd", "y_fused", "z_inv", "x_inv", "finalize")
 KERNEL_NAMES = {"x_fwd": "k_x_fwd", "z_fwd": "k_c2c", "y_fused": "k_fused", "z_inv": "k_c2c",
                 "x_inv": "k_x_inv", "finalize": "k_finalize"}
-
-
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2210_06232_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".h", ".hip")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + f.read())
-    return h.hexdigest()[:16]
 
 
 def measured_traffic(prec: str, kernel: str):
@@ -63,12 +53,6 @@ def measured_traffic(prec: str, kernel: str):
         return float(ent["fetch_bytes"]) + float(ent["write_bytes"])
     except (KeyError, ValueError, TypeError):
         return None
-
-
-def make_inputs():
-    from paper_2210_06232_amd import inputs
-    nx, ny, nz = WORKLOAD["grid"]
-    return inputs.random_fields((nx, ny, nz), tuple(WORKLOAD["domain"]), workload=2, p=2.0)
 
 
 def run_gpu(H, E, prec: str, steps: int, warmup: int):
@@ -122,12 +106,38 @@ def cpu_baseline(H, E):
             "seconds": round(dt, 2)}
 
 
+def serving(n_requests: int):
+    from paper_2210_06232_amd import serving as sv
+
+    def note(msg):
+        print(f"[bench] serving {msg}", file=sys.stderr, flush=True)
+
+    lat = sv.run_stream(n_requests, load=0.8, pool=1, modes=("batched", "serial_fp64"), progress=note)
+    thr = sv.run_stream(n_requests, pool=1, modes=("batched", "serial_fp64"), burst=True, progress=note)
+
+    def pick(r):
+        keys = ("p50_s", "p99_s", "slowdown_p50", "slowdown_p99", "point_steps_per_s", "wall_s", "completed",
+                "failed", "peak_running", "mean_batch", "peak_bytes")
+        return {k: (round(r[k], 6) if isinstance(r[k], float) else r[k]) for k in keys}
+
+    return {
+        "stream": f"{n_requests} requests, grids 32^3..256^3 and 64x128x256, 70% fp32, nsteps log-uniform "
+                  "[10,5000], cadence U{10..500}, budget 24 GB, max batch 32",
+        "latency_load0.8": {"rate_per_s": round(lat["rate_per_s"], 4), "batched": pick(lat["batched"]),
+                            "serial_fp64": pick(lat["serial_fp64"])},
+        "throughput_burst": {"batched": pick(thr["batched"]), "serial_fp64": pick(thr["serial_fp64"]),
+                             "speedup_vs_serial_fp64": round(thr["batched"]["point_steps_per_s"]
+                                                             / thr["serial_fp64"]["point_steps_per_s"], 3)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48, help="requests per serving replay (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -135,19 +145,24 @@ def main():
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
 
-    H, E = make_inputs()
+    H, E = headline_inputs()
     print(f"[bench] inputs ready {H.shape}", file=sys.stderr, flush=True)
     r64 = run_gpu(H, E, "fp64", args.steps, args.warmup)
     print(f"[bench] fp64 {r64['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
     r32 = run_gpu(H, E, "fp32", args.steps, args.warmup)
     print(f"[bench] fp32 {r32['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
+    serve = None
+    if args.serve_requests > 0:
+        serve = serving(args.serve_requests)
+        print(f"[bench] serving p50 {serve['latency_load0.8']['batched']['p50_s']:.3f} s", file=sys.stderr,
+              flush=True)
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
         cpu = cpu_baseline(H, E)
         print(f"[bench] cpu oracle {cpu['seconds']} s/step", file=sys.stderr, flush=True)
 
     out = {
-        "metric": "field-point-steps/s at 256^3 FP64 vs FP32 (% HBM roofline)",
+        "metric": "field-point-steps/s at 256^3 FP64 vs FP32 (% HBM roofline); served p50/p99 latency",
         "value": r64["value"],
         "unit": "field-point-steps/s",
         "n_gpus": 1,
@@ -165,6 +180,7 @@ def main():
         "pass_ms_per_step": r64["pass_ms_per_step"],
         "fp32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
                  "roofline": r32["roofline"], "pass_ms_per_step": r32["pass_ms_per_step"]},
+        "serving": serve,
         "kernel_source_hash": kernel_source_hash(),
     }
     if rank == 0:

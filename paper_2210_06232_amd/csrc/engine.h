@@ -63,8 +63,9 @@ struct Engine {
     // One step (mode Z_STEP: x, z, fused y, z^-1, x^-1, finalize) or a forward-only
     // evaluation of the invariants (mode Z_FORWARD: state -> work, nothing stored back),
     // for nm members described by the device array md.  ev: 7 events recorded around
-    // the kernels (or null).
-    eifp_status passes(int mode, const void* md, int nm, hipStream_t st, hipEvent_t* ev) const;
+    // the kernels (or null).  want_inv = false skips the invariant partial sums and the
+    // finalize (a step between output points).
+    eifp_status passes(int mode, const void* md, int nm, hipStream_t st, hipEvent_t* ev, bool want_inv = true) const;
     // unscaled forward transform of each member's state into its work buffer
     eifp_status forward_spectrum(const void* md, int nm, hipStream_t st) const;
 };

@@ -47,14 +47,16 @@ eifp_status rc_to_status(int rc, const char* what) {
 }
 
 template <typename T>
-eifp_status run_passes(const Engine& en, int mode, const void* md, int nm, hipStream_t st, hipEvent_t* ev) {
+eifp_status run_passes(const Engine& en, int mode, const void* md, int nm, hipStream_t st, hipEvent_t* ev,
+                       bool want_inv) {
     int rc;
     if (ev) EIFP_HIP_TRY(hipEventRecord(ev[0], st));
     if ((rc = launch_x<T>(false, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x forward");
     if (ev) EIFP_HIP_TRY(hipEventRecord(ev[1], st));
     if ((rc = launch_c2c<T>(false, AXIS_Z, en.g, md, nm, en.twz, st))) return rc_to_status(rc, "z forward");
     if (ev) EIFP_HIP_TRY(hipEventRecord(ev[2], st));
-    if ((rc = launch_fused<T>(mode, AXIS_Y, en.g, md, nm, en.twy, 1, st))) return rc_to_status(rc, "fused y pass");
+    if ((rc = launch_fused<T>(mode, AXIS_Y, en.g, md, nm, en.twy, want_inv ? 1 : 0, st)))
+        return rc_to_status(rc, "fused y pass");
     if (ev) EIFP_HIP_TRY(hipEventRecord(ev[3], st));
     if (mode == Z_STEP) {
         if ((rc = launch_c2c<T>(true, AXIS_Z, en.g, md, nm, en.twz, st))) return rc_to_status(rc, "z inverse");
@@ -65,7 +67,7 @@ eifp_status run_passes(const Engine& en, int mode, const void* md, int nm, hipSt
         EIFP_HIP_TRY(hipEventRecord(ev[4], st));
         EIFP_HIP_TRY(hipEventRecord(ev[5], st));
     }
-    if ((rc = launch_finalize<T>(md, nm, en.nparts, st))) return rc_to_status(rc, "finalize");
+    if (want_inv && (rc = launch_finalize<T>(md, nm, en.nparts, st))) return rc_to_status(rc, "finalize");
     if (ev) EIFP_HIP_TRY(hipEventRecord(ev[6], st));
     return EIFP_OK;
 }
@@ -173,9 +175,9 @@ void Engine::release() {
     twx = twy = twz = nullptr;
 }
 
-eifp_status Engine::passes(int mode, const void* md, int nm, hipStream_t st, hipEvent_t* ev) const {
-    return prec == EIFP_FP64 ? run_passes<double>(*this, mode, md, nm, st, ev)
-                             : run_passes<float>(*this, mode, md, nm, st, ev);
+eifp_status Engine::passes(int mode, const void* md, int nm, hipStream_t st, hipEvent_t* ev, bool want_inv) const {
+    return prec == EIFP_FP64 ? run_passes<double>(*this, mode, md, nm, st, ev, want_inv)
+                             : run_passes<float>(*this, mode, md, nm, st, ev, want_inv);
 }
 
 eifp_status Engine::forward_spectrum(const void* md, int nm, hipStream_t st) const {

@@ -88,7 +88,7 @@ struct Group {
     bool in_flight = false;
     int k = 0;                       // steps in flight
     int nm_flight = 0;
-    std::map<int, hipGraphExec_t> graphs;
+    std::map<std::pair<int, bool>, hipGraphExec_t> graphs;  // (batch size, with invariants)
     double ms_per_member_step = 0;   // running estimate
     int readers = 0;
 };
@@ -368,10 +368,10 @@ long long next_boundary(const Req* r) {
     return b;
 }
 
-eifp_status capture_step_graph(Group* g, int nm, hipGraphExec_t* out) {
+eifp_status capture_step_graph(Group* g, int nm, bool want_inv, hipGraphExec_t* out) {
     hipGraph_t graph = nullptr;
     EIFP_HIP_TRY(hipStreamBeginCapture(g->st, hipStreamCaptureModeThreadLocal));
-    const eifp_status st = g->en.passes(Z_STEP, g->desc_dev, nm, g->st, nullptr);
+    const eifp_status st = g->en.passes(Z_STEP, g->desc_dev, nm, g->st, nullptr, want_inv);
     const hipError_t e = hipStreamEndCapture(g->st, &graph);
     if (st) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -403,25 +403,27 @@ eifp_status launch_chunk(eifp_server* sv, Group* g) {
             }
             EIFP_HIP_TRY(hipMemcpyAsync(g->desc_dev, g->desc_host, nm * sizeof(DescImage), hipMemcpyHostToDevice, g->st));
         }
-        hipGraphExec_t ge = nullptr;
-        if (!(sv->flags & EIFP_SERVER_NO_GRAPHS)) {
-            auto it = g->graphs.find(nm);
-            if (it == g->graphs.end()) {
-                eifp_status st = capture_step_graph(g, nm, &ge);
-                if (st) return st;
-                g->graphs[nm] = ge;
-            } else {
-                ge = it->second;
-            }
-        }
+        // invariants are reduced only on the chunk's last step, and only if a member
+        // reaches an output point there
+        bool out_at_end = false;
+        for (Req* r : g->members) out_at_end |= r->done + k == next_boundary(r);
         EIFP_HIP_TRY(hipEventRecord(g->ev0, g->st));
         for (long long s = 0; s < k; ++s) {
-            if (ge) {
-                EIFP_HIP_TRY(hipGraphLaunch(ge, g->st));
-            } else {
-                eifp_status st = g->en.passes(Z_STEP, g->desc_dev, nm, g->st, nullptr);
+            const bool inv = out_at_end && s == k - 1;
+            if (sv->flags & EIFP_SERVER_NO_GRAPHS) {
+                eifp_status st = g->en.passes(Z_STEP, g->desc_dev, nm, g->st, nullptr, inv);
                 if (st) return st;
+                continue;
             }
+            hipGraphExec_t& ge = g->graphs[std::make_pair(nm, inv)];
+            if (!ge) {
+                eifp_status st = capture_step_graph(g, nm, inv, &ge);
+                if (st) {
+                    g->graphs.erase(std::make_pair(nm, inv));
+                    return st;
+                }
+            }
+            EIFP_HIP_TRY(hipGraphLaunch(ge, g->st));
         }
         for (Req* r : g->members)
             if (r->snap && r->done + k == next_boundary(r) && r->done + k < r->rq.nsteps)

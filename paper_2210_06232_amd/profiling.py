@@ -1,0 +1,124 @@
+"""Workload and summary for the rocprofv3 HBM-traffic counters of the headline step.
+
+Counters are taken in two runs of their own (FETCH_SIZE, then WRITE_SIZE: the two do
+not fit one pass):
+
+  rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o run --output-format csv -- \\
+      python3 paper_2210_06232_amd/profiling.py run
+  rocprofv3 --pmc WRITE_SIZE -d OUT/write -o run --output-format csv -- \\
+      python3 paper_2210_06232_amd/profiling.py run
+  python3 paper_2210_06232_amd/profiling.py summarize OUT/fetch OUT/write
+
+`run` does a few FP64 and FP32 steps of the headline workload, then three plain device
+copies of a known size (the copy kernel calibrates the counters: its true traffic is
+the buffer size read plus the buffer size written).  `summarize` writes
+profiles/traffic_256cubed.json: per kernel and precision, HBM bytes per launch from
+the counters scaled by the copy's factor, stamped with the hash of the kernel sources
+they were taken on.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+COPY_BYTES = 6 * 256 ** 3 * 8  # one FP64 state of the headline grid
+OUT_JSON = os.path.join(ROOT, "profiles", "traffic_256cubed.json")
+
+
+# the sources that define the step's kernels and their launch shapes
+KERNEL_SOURCES = ("fft_core.h", "kernels.h", "passes.h", "passes_impl.h", "passes_f64.hip", "passes_f32.hip")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2210_06232_amd", "csrc")
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def run(steps: int = 3):
+    import torch
+    from paper_2210_06232_amd import eifp
+    from paper_2210_06232_amd.workload import HEADLINE, headline_inputs
+    H, E = headline_inputs()
+    for prec in ("fp64", "fp32"):
+        with eifp.Solver(H, E, HEADLINE["domain"], HEADLINE["mu"], HEADLINE["eps"], prec) as s:
+            s.step(HEADLINE["tau"], steps)
+            s.sync()
+        print(f"[profiling] {prec}: {steps} steps", flush=True)
+    x = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    x.fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print("[profiling] copies done", flush=True)
+
+
+def _rows(d: str, counter: str):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    for fn in files:
+        with open(fn) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    yield r["Kernel_Name"], int(r["Dispatch_Id"]), float(r["Counter_Value"])
+
+
+def _per_kernel(rows):
+    """{(prec, name): [KiB per dispatch]} for the library kernels; copy dispatches apart."""
+    out, copies = {}, []
+    for name, _, v in rows:
+        m = re.search(r"(k_[a-z0-9_]+)<(double|float)", name)
+        if m:
+            key = ("fp64" if m.group(2) == "double" else "fp32", m.group(1))
+            out.setdefault(key, []).append(v)
+        elif "copy" in name.lower():
+            copies.append(v)
+    return out, copies
+
+
+def summarize(fetch_dir: str, write_dir: str, out_path: str = OUT_JSON):
+    fk, fc = _per_kernel(_rows(fetch_dir, "FETCH_SIZE"))
+    wk, wc = _per_kernel(_rows(write_dir, "WRITE_SIZE"))
+    # the calibration copies are the largest copy dispatches
+    big_f = [v for v in fc if v >= 0.5 * max(fc)]
+    big_w = [v for v in wc if v >= 0.5 * max(wc)]
+    f_kib, w_kib = sum(big_f) / len(big_f), sum(big_w) / len(big_w)
+    ff, fw = COPY_BYTES / (f_kib * 1024.0), COPY_BYTES / (w_kib * 1024.0)
+    kernels = {}
+    for key in sorted(set(fk) | set(wk)):
+        prec, name = key
+        fv, wv = fk.get(key, [0.0]), wk.get(key, [0.0])
+        f_mean, w_mean = sum(fv) / len(fv), sum(wv) / len(wv)
+        kernels.setdefault(prec, {})[name] = {
+            "dispatches": len(fv), "fetch_kib_raw": round(f_mean, 1), "write_kib_raw": round(w_mean, 1),
+            "fetch_bytes": round(f_mean * 1024.0 * ff), "write_bytes": round(w_mean * 1024.0 * fw)}
+    rec = {"source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES,
+           "copy_fetch_kib_raw": round(f_kib, 1), "copy_write_kib_raw": round(w_kib, 1),
+           "factor_fetch": ff, "factor_write": fw, "kernels": kernels,
+           "note": "bytes per launch; one launch of a pass covers all six components of the 256^3 state"}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+if __name__ == "__main__":
+    if len(sys.argv) >= 2 and sys.argv[1] == "run":
+        run(int(sys.argv[2]) if len(sys.argv) > 2 else 3)
+    elif len(sys.argv) >= 4 and sys.argv[1] == "summarize":
+        summarize(sys.argv[2], sys.argv[3])
+    else:
+        raise SystemExit(__doc__)
