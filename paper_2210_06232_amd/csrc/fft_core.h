@@ -295,6 +295,11 @@ __device__ __forceinline__ void fft_pencil(cpx<T> (&v)[P::E], int t, Lds& lds, c
 #define EIFP_LDS_PAD 1
 #endif
 __host__ __device__ constexpr int col_pitch(int B) { return B + EIFP_LDS_PAD; }
+// pad of the fused pass's exchange buffers (its narrow tiles measure best unpadded)
+#ifndef EIFP_ZPAD
+#define EIFP_ZPAD 0
+#endif
+__host__ __device__ constexpr int zcol_pitch(int B) { return B + EIFP_ZPAD; }
 // after_load(): a single buffer needs a second barrier before it is written again; the
 // double-buffered views flip to the other buffer instead, which is safe because the
 // next write to this buffer comes after the next exchange's barrier.
@@ -311,7 +316,7 @@ struct LdsCols {
 
 // Two alternating [pos][col] buffers of PLANE reals per plane (re, im): one barrier per
 // exchange.  base holds re0, im0, re1, im1.
-template <typename T, int B, int PLANE>
+template <typename T, int B, int PLANE, int PITCH = col_pitch(B)>
 struct LdsCols2 {
     T* base;
     int c;
@@ -319,12 +324,12 @@ struct LdsCols2 {
     __device__ __forceinline__ T* re() const { return base + (2 * cur) * PLANE; }
     __device__ __forceinline__ void st(int pos, cpx<T> a) {
         T* r = re();
-        r[pos * col_pitch(B) + c] = a.x;
-        r[PLANE + pos * col_pitch(B) + c] = a.y;
+        r[pos * PITCH + c] = a.x;
+        r[PLANE + pos * PITCH + c] = a.y;
     }
     __device__ __forceinline__ cpx<T> ld(int pos) const {
         const T* r = re();
-        return {r[pos * col_pitch(B) + c], r[PLANE + pos * col_pitch(B) + c]};
+        return {r[pos * PITCH + c], r[PLANE + pos * PITCH + c]};
     }
     __device__ __forceinline__ void sync() { __syncthreads(); }
     __device__ __forceinline__ void after_load() { cur ^= 1; }

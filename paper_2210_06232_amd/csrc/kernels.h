@@ -173,6 +173,32 @@ __device__ __forceinline__ void store_col(const cpx<T> (&v)[P::E], __amdgpu_buff
 }
 
 // ---------------------------------------------------------------------------------
+// tile numbering
+// ---------------------------------------------------------------------------------
+// The dispatcher deals workgroups to the 8 XCDs round robin by linear id, and each XCD
+// has its own L2.  With `on`, (blockIdx.x, blockIdx.y) are renumbered so that the
+// workgroups one XCD receives (linear ids congruent mod 8) cover a contiguous range of
+// tiles: neighbouring tiles, which share cache lines and DRAM pages, then run on the
+// same XCD at about the same time.  A bijection whenever gridDim.x * gridDim.y is a
+// multiple of 8 (otherwise the ids are left as they are).
+#ifndef EIFP_FUSED_XCD
+#define EIFP_FUSED_XCD 1
+#endif
+#ifndef EIFP_C2C_XCD
+#define EIFP_C2C_XCD 0
+#endif
+__device__ __forceinline__ void xcd_tiles(bool on, int& tx, int& ty) {
+    tx = (int)blockIdx.x;
+    ty = (int)blockIdx.y;
+    const unsigned n = gridDim.x * gridDim.y;
+    if (!on || (n & 7u) != 0) return;
+    const unsigned L = blockIdx.x + gridDim.x * blockIdx.y;
+    const unsigned Lp = (L & 7u) * (n >> 3) + (L >> 3);
+    tx = (int)(Lp % gridDim.x);
+    ty = (int)(Lp / gridDim.x);
+}
+
+// ---------------------------------------------------------------------------------
 // single-component C2C pass along a strided axis (y or z), one component per workgroup
 // ---------------------------------------------------------------------------------
 // Pencil positions are pstride apart; the third (outer) axis index blockIdx.y is ostride
@@ -188,8 +214,10 @@ k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, l
     __shared__ cpx<T> s_tw[NP];
     stage_table(s_tw, tw, NP);
     const int c = threadIdx.x % B, t = threadIdx.x / B;
-    const int col = blockIdx.x * B + c;
-    const int o = blockIdx.y;
+    int tx, ty;
+    xcd_tiles(EIFP_C2C_XCD, tx, ty);
+    const int col = tx * B + c;
+    const int o = ty;
     const int member = blockIdx.z / 6, comp = blockIdx.z % 6;
     const bool active = col < M;
     const __amdgpu_buffer_rsrc_t r = make_rsrc(md[member].work + comp * cs, (unsigned)(cs * sizeof(cpx<T>)));
@@ -314,24 +342,33 @@ __device__ __forceinline__ void propagate_mode(cpx<T>* h, cpx<T>* e, double bx, 
 
 // Minimum waves per SIMD requested for the fused kernel (caps its register budget).
 #ifndef EIFP_ZWAVES64
-#define EIFP_ZWAVES64 2
+#define EIFP_ZWAVES64 1
 #endif
 #ifndef EIFP_ZWAVES32
 #define EIFP_ZWAVES32 2
 #endif
-template <typename T> struct ZWaves { static constexpr int value = sizeof(T) == 8 ? EIFP_ZWAVES64 : EIFP_ZWAVES32; };
+template <typename T, int N> struct ZWaves {
+    // lengths with a factor 3 (6 values per thread in FP64, 12 in FP32): one wave
+    static constexpr int value = (N % 3 == 0) ? 1 : (sizeof(T) == 8 ? EIFP_ZWAVES64 : EIFP_ZWAVES32);
+};
+
+// scheduling fences of the fused pass: bit 0 between components' transforms, bit 1
+// between modes of the propagator
+#ifndef EIFP_FUSED_SB
+#define EIFP_FUSED_SB 3
+#endif
 
 // The fused pass transforms, propagates and transforms back along one strided axis.
 // AXIS = 1: pencils along y (stride M), one tile row per z index; AXIS = 2: pencils along
 // z (stride Ny M), one tile row per y index.  Strides in complex elements; cs is the
 // component stride.  Grid: (x tiles, outer, members); each block writes one partial
-// record, at index blockIdx.y * gridDim.x + blockIdx.x of its member's partials.
+// record, at index (tile row) * gridDim.x + (tile column) of its member's partials.
 template <typename T, class P, int B, int MODE, int AXIS>
-__global__ void __launch_bounds__(P::T * B, ZWaves<T>::value)
+__global__ void __launch_bounds__(P::T * B, (ZWaves<T, P::N>::value))
 k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, long ostride, long cs,
         const cpx<T>* __restrict__ tw, int want_inv) {
     constexpr int NZ = P::N, E = P::E, TT = P::T, NT = P::T * B;
-    __shared__ T s_x[2 * 2 * NZ * col_pitch(B)];
+    __shared__ T s_x[2 * 2 * NZ * zcol_pitch(B)];
     __shared__ cpx<T> s_tw[NZ];
     __shared__ double s_red[((NT + 63) / 64) * INV_NPART];
     stage_table(s_tw, tw, NZ);
@@ -339,13 +376,15 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
     const PropParams pp = mem.pp;
     cpx<T>* buf = mem.work;
     const int c = threadIdx.x % B, t = threadIdx.x / B;
-    const int col = blockIdx.x * B + c;
-    const int o = blockIdx.y;
+    int tx, ty;
+    xcd_tiles(EIFP_FUSED_XCD, tx, ty);
+    const int col = tx * B + c;
+    const int o = ty;
     const bool active = col < M;
     const unsigned cbytes = (unsigned)cs * sizeof(cpx<T>);
     const unsigned voff = (unsigned)(t * pstride + o * ostride + (active ? col : M - 1)) * sizeof(cpx<T>);
     const unsigned sstep = (unsigned)(TT * pstride) * sizeof(cpx<T>);
-    LdsCols2<T, B, NZ * col_pitch(B)> lds{s_x, c, 0};
+    LdsCols2<T, B, NZ * zcol_pitch(B), zcol_pitch(B)> lds{s_x, c, 0};
 
     cpx<T> v[6][E];
 #pragma unroll
@@ -358,7 +397,7 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
         asm volatile("" : "+v"(tq), "+v"(cq));
         lds.c = cq;
         fft_pencil<P, false, 1>(v[q], tq, lds, s_tw);
-        __builtin_amdgcn_sched_barrier(0);  // one component's temporaries live at a time
+        if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);  // one component's temporaries live at a time
     }
 
     const double bx = col == 0 ? 0.0 : pp.nu[0] * (double)col;  // packed column: Omega_x = 0 at 0 and Nx/2
@@ -393,10 +432,10 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
                 v[3 + q][i] = e[q];
             }
         }
-        __builtin_amdgcn_sched_barrier(0);  // one mode's temporaries live at a time
+        if (EIFP_FUSED_SB & 2) __builtin_amdgcn_sched_barrier(0);  // one mode's temporaries live at a time
     }
     if (want_inv)
-        block_reduce_store<NT>(acc, mem.partials + ((long)blockIdx.y * gridDim.x + blockIdx.x) * INV_NPART, s_red);
+        block_reduce_store<NT>(acc, mem.partials + ((long)ty * gridDim.x + tx) * INV_NPART, s_red);
     if (MODE == Z_STEP) {
         // inverse transform and store each component as soon as it is done; Z_FORWARD
         // leaves memory untouched
@@ -408,7 +447,7 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
             lds.c = cq;
             fft_pencil<P, true, 1>(v[q], tq, lds, s_tw);
             store_col<T, P>(v[q], make_rsrc(buf + q * cs, cbytes), voff, sstep, active);
-            __builtin_amdgcn_sched_barrier(0);
+            if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
         }
     }
 }

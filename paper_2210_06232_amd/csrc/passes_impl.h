@@ -7,22 +7,30 @@ namespace eifp {
 
 // values per thread for the single-component passes (x, y, z): radix-16/12 plans
 template <int N> struct XYE { static constexpr int E = (N % 3 == 0) ? (N >= 12 ? 12 : N) : (N >= 16 ? 16 : N); };
-// values per thread for the fused pass, which holds six components at once: 4 or 6
-// in FP64, 8 or 12 in FP32 (keeps the six pencils in registers without spilling)
+// values per thread for the fused pass, which holds six components at once: 8 in FP64,
+// with one wave per SIMD and the accumulation registers as the overflow of the six
+// pencils; 8 in FP32 at two waves per SIMD; lengths with a factor 3 below
 #ifndef EIFP_ZE64
-#define EIFP_ZE64 4
+#define EIFP_ZE64 8
 #endif
 #ifndef EIFP_ZE32
 #define EIFP_ZE32 8
 #endif
 template <typename T, int N> struct ZE {
     static constexpr int E2 = sizeof(T) == 8 ? EIFP_ZE64 : EIFP_ZE32;  // for powers of two
-    static constexpr int E = sizeof(T) == 8 ? ((N % 3 == 0) ? 6 : (N >= E2 ? E2 : N))
-                                            : ((N % 3 == 0) ? (N >= 12 ? 12 : N) : (N >= E2 ? E2 : N));
+    // lengths with a factor 3: 6 per thread in FP64, 12 in FP32 (fewer stages), both at
+    // one wave per SIMD
+    static constexpr int E3 = sizeof(T) == 8 ? 6 : 12;
+    static constexpr int E = (N % 3 == 0) ? (N >= E3 ? E3 : N) : (N >= E2 ? E2 : N);
 };
 
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int pow2floor(int a) {  // largest power of two <= a (a >= 1)
+    int p = 1;
+    while (2 * p <= a) p *= 2;
+    return p;
+}
 
 template <typename T, int M> struct XCfg {
     using P = Plan<M, XYE<M>::E>;
@@ -36,21 +44,29 @@ template <typename T, int M> struct XCfg {
 template <typename T, int N> struct CCfg {
     using P = Plan<N, XYE<N>::E>;
     static constexpr int B0 = cmin(64, cmax(EIFP_CROW_BYTES / (2 * (int)sizeof(T)), 256 / P::T));
-    // at most 1024 threads and ~72 KB of LDS ([pos][col] pitch B + pad, two planes)
-    static constexpr int B =
-        cmax(1, cmin(cmin(B0, 1024 / P::T), (72 * 1024) / (N * 2 * (int)sizeof(T)) - EIFP_LDS_PAD));
+    // at most 1024 threads and 80 KB of LDS ([pos][col] pitch B + pad, two planes), a
+    // power of two so that tiles stay aligned to the row segments
+    static constexpr int B = pow2floor(
+        cmax(1, cmin(cmin(B0, 1024 / P::T), (80 * 1024) / (N * 2 * (int)sizeof(T)) - EIFP_LDS_PAD)));
 };
 
 // Row segment targeted by a tile of the fused pass; its double-buffered exchange takes
 // 4 N (B + pad) sizeof(T) bytes of LDS.
+// Tiles of the fused pass are narrow (64-byte row segments; 128-thread workgroups at
+// the least) so that two or more workgroups share a CU and overlap their load, compute
+// and store phases; the tiles are numbered XCD by XCD (xcd_tiles) so that the two
+// halves of a 128-byte line are read by the same L2.
 #ifndef EIFP_ZROW_BYTES
-#define EIFP_ZROW_BYTES 128
+#define EIFP_ZROW_BYTES 64
+#endif
+#ifndef EIFP_ZMIN_THREADS
+#define EIFP_ZMIN_THREADS 128
 #endif
 template <typename T, int N> struct ZCfg {
     using P = Plan<N, ZE<T, N>::E>;
-    static constexpr int B0 = cmin(64, cmax(EIFP_ZROW_BYTES / (2 * (int)sizeof(T)), 256 / P::T));
-    static constexpr int B =
-        cmax(1, cmin(cmin(B0, 1024 / P::T), (96 * 1024) / (N * 4 * (int)sizeof(T)) - EIFP_LDS_PAD));
+    static constexpr int B0 = cmin(64, cmax(EIFP_ZROW_BYTES / (2 * (int)sizeof(T)), EIFP_ZMIN_THREADS / P::T));
+    static constexpr int B = pow2floor(
+        cmax(1, cmin(cmin(B0, 1024 / P::T), (96 * 1024) / (N * 4 * (int)sizeof(T)) - EIFP_ZPAD)));
 };
 
 inline int check_launch() { return hipGetLastError() == hipSuccess ? kOk : kLaunchFailed; }
