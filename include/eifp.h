@@ -85,6 +85,23 @@ eifp_status eifp_init(eifp_solver **out, int nx, int ny, int nz, const eifp_doma
  * no-op.  Errors: INVALID_ARG (NULL solver, non-finite tau, nsteps < 0), DEVICE. */
 eifp_status eifp_step(eifp_solver *s, double tau, long long nsteps);
 
+/* Anchor: store the spectrum of the current state (its forward 3-D transform, Def. 2.3
+ * step 2) on the device as the starting point of later eifp_jump calls.  Allocates one
+ * state-sized device buffer on first use.  Enqueued.  Errors: INVALID_ARG, OUT_OF_MEMORY,
+ * DEVICE. */
+eifp_status eifp_anchor(eifp_solver *s);
+
+/* Same result as eifp_step(s, tau, nsteps) up to rounding, computed in one propagation
+ * from the anchor: the scheme is the exact flow of the Fourier semi-discretisation over
+ * any time span (Def. 2.3, Prop. 2.1; Alg. 2 takes t_end in one step), so the new state
+ * is the inverse transform of the anchored spectrum propagated over
+ * (t + tau * nsteps - t_anchor).  Rounding errors therefore do not accumulate with the
+ * number of steps (one forward transform at the anchor, one propagation and inverse
+ * transform per call).  Anchors the current state first if there is no valid anchor;
+ * eifp_step invalidates the anchor.  Invariants are computed for the new state.  Errors:
+ * as eifp_step, plus OUT_OF_MEMORY (first anchor). */
+eifp_status eifp_jump(eifp_solver *s, double tau, long long nsteps);
+
 /* Same as eifp_step, and also measures each pass with HIP events recorded on the
  * solver's stream around every kernel.  pass_ms[0..5] receive the summed durations in
  * milliseconds of: x-forward (real-to-complex), z-forward, fused y (forward,

@@ -37,6 +37,7 @@ struct DescImage {
     void* work;
     double* partials;
     double* inv;
+    const void* spec;
     PropParams pp;
 };
 static_assert(sizeof(DescImage) == sizeof(MemberDesc<double>), "descriptor layout");
@@ -68,6 +69,10 @@ struct Engine {
     eifp_status passes(int mode, const void* md, int nm, hipStream_t st, hipEvent_t* ev, bool want_inv = true) const;
     // unscaled forward transform of each member's state into its work buffer
     eifp_status forward_spectrum(const void* md, int nm, hipStream_t st) const;
+    // Jump: each member's state becomes the exact flow over its tau of its anchored
+    // spectrum (fused propagate + inverse y from spec into work == state, z^-1, x^-1),
+    // with the invariants if want_inv.
+    eifp_status jump(const void* md, int nm, hipStream_t st, bool want_inv = true) const;
 };
 
 // Widen / narrow n reals on the device (enqueued on st).

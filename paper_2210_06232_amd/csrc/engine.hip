@@ -81,6 +81,17 @@ eifp_status run_spectrum(const Engine& en, const void* md, int nm, hipStream_t s
     return EIFP_OK;
 }
 
+template <typename T>
+eifp_status run_jump(const Engine& en, const void* md, int nm, hipStream_t st, bool want_inv) {
+    int rc;
+    if ((rc = launch_fused<T>(Z_JUMP, AXIS_Y, en.g, md, nm, en.twy, want_inv ? 1 : 0, st)))
+        return rc_to_status(rc, "fused jump pass");
+    if ((rc = launch_c2c<T>(true, AXIS_Z, en.g, md, nm, en.twz, st))) return rc_to_status(rc, "z inverse");
+    if ((rc = launch_x<T>(true, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x inverse");
+    if (want_inv && (rc = launch_finalize<T>(md, nm, en.nparts, st))) return rc_to_status(rc, "finalize");
+    return EIFP_OK;
+}
+
 template <typename TO, typename TI>
 eifp_status convert(const void* in, void* out, long long n, hipStream_t st) {
     const long long blocks = (n + 255) / 256;
@@ -182,6 +193,11 @@ eifp_status Engine::passes(int mode, const void* md, int nm, hipStream_t st, hip
 
 eifp_status Engine::forward_spectrum(const void* md, int nm, hipStream_t st) const {
     return prec == EIFP_FP64 ? run_spectrum<double>(*this, md, nm, st) : run_spectrum<float>(*this, md, nm, st);
+}
+
+eifp_status Engine::jump(const void* md, int nm, hipStream_t st, bool want_inv) const {
+    return prec == EIFP_FP64 ? run_jump<double>(*this, md, nm, st, want_inv)
+                             : run_jump<float>(*this, md, nm, st, want_inv);
 }
 
 eifp_status convert_f32_to_f64(const void* in, void* out, long long n, hipStream_t st) {

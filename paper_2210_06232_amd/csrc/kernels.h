@@ -39,14 +39,16 @@ struct PropParams {
 
 // One member of a batch.  state: the solve's six fields (x-forward source, x-inverse
 // destination); work: the buffer the transforms run in (== state for a step, a scratch
-// buffer for a forward-only evaluation); partials: ntiles records of INV_NPART doubles;
-// inv: the finalized invariants (8 doubles).
+// or anchor buffer for a forward-only transform); partials: ntiles records of
+// INV_NPART doubles; inv: the finalized invariants (8 doubles); spec: the anchored
+// spectrum a jump propagates from (unused otherwise).
 template <typename T>
 struct MemberDesc {
     cpx<T>* state;
     cpx<T>* work;
     double* partials;
     double* inv;
+    const cpx<T>* spec;
     PropParams pp;
 };
 
@@ -233,7 +235,11 @@ k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, l
 // ---------------------------------------------------------------------------------
 // fused pass: forward, propagate, invariant partials, inverse (all six components)
 // ---------------------------------------------------------------------------------
-enum ZMode { Z_STEP = 0, Z_FORWARD = 1 };
+// Z_STEP: forward, propagate by the member's tau, partials, inverse (one time step).
+// Z_FORWARD: forward, partials only (invariants of the state; memory untouched).
+// Z_JUMP: read the anchored spectrum (all three forward transforms already done),
+// propagate by the member's tau, partials, inverse along the fused axis into work.
+enum ZMode { Z_STEP = 0, Z_FORWARD = 1, Z_JUMP = 2 };
 
 template <typename T>
 __device__ __forceinline__ double dreal(T a) { return (double)a; }
@@ -387,17 +393,20 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
     LdsCols2<T, B, NZ * zcol_pitch(B), zcol_pitch(B)> lds{s_x, c, 0};
 
     cpx<T> v[6][E];
+    const cpx<T>* src = MODE == Z_JUMP ? mem.spec : buf;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) load_col<T, P>(v[q], make_rsrc(buf + q * cs, cbytes), voff, sstep);
+    for (int q = 0; q < 6; ++q) load_col<T, P>(v[q], make_rsrc(src + q * cs, cbytes), voff, sstep);
+    if (MODE != Z_JUMP) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        // re-derive the lane indices per component so that LDS addresses are recomputed
-        // (cheap ALU) instead of being kept live across all twelve transforms
-        int tq = t, cq = c;
-        asm volatile("" : "+v"(tq), "+v"(cq));
-        lds.c = cq;
-        fft_pencil<P, false, 1>(v[q], tq, lds, s_tw);
-        if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);  // one component's temporaries live at a time
+        for (int q = 0; q < 6; ++q) {
+            // re-derive the lane indices per component so that LDS addresses are
+            // recomputed (cheap ALU) instead of being kept live across all transforms
+            int tq = t, cq = c;
+            asm volatile("" : "+v"(tq), "+v"(cq));
+            lds.c = cq;
+            fft_pencil<P, false, 1>(v[q], tq, lds, s_tw);
+            if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);  // one component's temporaries live at a time
+        }
     }
 
     const double bx = col == 0 ? 0.0 : pp.nu[0] * (double)col;  // packed column: Omega_x = 0 at 0 and Nx/2
@@ -408,13 +417,15 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
     const double w = col == 0 ? 1.0 : 2.0;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-        const int kp = t + TT * m_last<P>(i);
+        // after a forward transform register i holds position m_last(i); loaded from the
+        // anchored spectrum it holds m_first(i), which is also what the inverse expects
+        const int kp = t + TT * (MODE == Z_JUMP ? m_first<P>(i) : m_last<P>(i));
         const double bp = omega(kp, NZ, AXIS == 1 ? pp.nu[1] : pp.nu[2]);
         const double by = AXIS == 1 ? bp : bo;
         const double bz = AXIS == 1 ? bo : bp;
         cpx<T> h[3] = {v[0][i], v[1][i], v[2][i]};
         cpx<T> e[3] = {v[3][i], v[4][i], v[5][i]};
-        if (MODE == Z_STEP) {
+        if (MODE != Z_FORWARD) {
             propagate_mode(h, e, bx, by, bz, pp);
         } else {
             const T s = (T)pp.inv_ns;
@@ -425,7 +436,7 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
             }
         }
         if (want_inv && active) accumulate_invariants(acc, w, bx, by, bz, h, e, pp);
-        if (MODE == Z_STEP) {
+        if (MODE != Z_FORWARD) {
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 v[q][i] = h[q];
@@ -436,12 +447,12 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
     }
     if (want_inv)
         block_reduce_store<NT>(acc, mem.partials + ((long)ty * gridDim.x + tx) * INV_NPART, s_red);
-    if (MODE == Z_STEP) {
+    if (MODE != Z_FORWARD) {
         // inverse transform and store each component as soon as it is done; Z_FORWARD
         // leaves memory untouched
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            last_to_first<P>(v[q]);
+            if (MODE == Z_STEP) last_to_first<P>(v[q]);
             int tq = t, cq = c;
             asm volatile("" : "+v"(tq), "+v"(cq));
             lds.c = cq;

@@ -34,7 +34,8 @@ template <typename T>
 int launch_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const void* tw, hipStream_t st);
 
 // fused pass along `axis` on each member's work buffer: mode Z_STEP (forward, propagate,
-// partials, inverse, store) or Z_FORWARD (forward, partials only; memory untouched)
+// partials, inverse, store), Z_FORWARD (forward, partials only; memory untouched) or
+// Z_JUMP (read the member's anchored spectrum, propagate, partials, inverse into work)
 template <typename T>
 int launch_fused(int mode, int axis, const Grid3& g, const void* md, int nm, const void* tw, int want_inv,
                  hipStream_t st);

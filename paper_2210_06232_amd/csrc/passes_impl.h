@@ -128,7 +128,9 @@ int run_fused(int mode, int axis, const Grid3& g, const void* md, int nm, const 
     // also covers z-fused pencils
     if (axis != AXIS_Y) return kUnsupported;
     if (mode == Z_STEP) run_fused_k<T, N, Z_STEP, AXIS_Y>(g, md, nm, tw, want_inv, st);
-    else run_fused_k<T, N, Z_FORWARD, AXIS_Y>(g, md, nm, tw, want_inv, st);
+    else if (mode == Z_FORWARD) run_fused_k<T, N, Z_FORWARD, AXIS_Y>(g, md, nm, tw, want_inv, st);
+    else if (mode == Z_JUMP) run_fused_k<T, N, Z_JUMP, AXIS_Y>(g, md, nm, tw, want_inv, st);
+    else return kUnsupported;
     return check_launch();
 }
 

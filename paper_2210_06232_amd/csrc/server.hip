@@ -399,7 +399,7 @@ eifp_status launch_chunk(eifp_server* sv, Group* g) {
             for (int i = 0; i < nm; ++i) {
                 Req* r = g->members[i];
                 g->desc_host[i] = DescImage{r->state, r->state, g->partials + (size_t)i * g->nparts * INV_NPART,
-                                            g->inv_dev + (size_t)i * 8, r->pp};
+                                            g->inv_dev + (size_t)i * 8, nullptr, r->pp};
             }
             EIFP_HIP_TRY(hipMemcpyAsync(g->desc_dev, g->desc_host, nm * sizeof(DescImage), hipMemcpyHostToDevice, g->st));
         }

@@ -6,8 +6,13 @@
 // followed by a one-workgroup finalize of the invariant partials.  The state stays in
 // HBM in the ABI's own layout ([6][nz][ny][nx] reals); all transforms are in place.
 // A solver is a batch of one member: the kernels read its buffers and scalars from a
-// two-entry device descriptor array (entry 0: step, entry 1: forward-only evaluation
-// into the scratch buffer).
+// four-entry device descriptor array (0: step; 1: forward-only evaluation into the
+// scratch buffer; 2: forward transform into the anchor buffer; 3: jump from the anchor).
+//
+// Jumps: the scheme is the exact flow of the Fourier semi-discretisation for any time
+// span (Def. 2.3; Alg. 2 takes t_end in one step), so the state after any number of
+// steps can be computed from one stored spectrum (the anchor) by one propagation and
+// one inverse transform, with the rounding of one step instead of one per step.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -30,9 +35,13 @@ struct eifp_solver {
     double* partials = nullptr;
     double* inv_dev = nullptr;
     double* inv_host = nullptr;  // pinned
-    void* desc_dev = nullptr;    // DescImage[2]
-    DescImage desc_host[2]{};
+    void* anchor = nullptr;      // anchored spectrum (allocated on first use)
+    bool anchor_valid = false;
+    double t_anchor = 0.0;
+    void* desc_dev = nullptr;    // DescImage[4]
+    DescImage desc_host[4]{};
     double desc_tau = 0.0;       // tau held by desc_dev[0]
+    double jump_span = 0.0;      // time span held by desc_dev[3]
     bool inv_current = false;    // inv_dev describes the current state
     double t = 0.0;
     long long steps = 0;
@@ -45,7 +54,7 @@ namespace {
 void release(eifp_solver* s) {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
-    for (void* p : {s->state, s->scratch, (void*)s->partials, (void*)s->inv_dev, s->desc_dev})
+    for (void* p : {s->state, s->scratch, s->anchor, (void*)s->partials, (void*)s->inv_dev, s->desc_dev})
         if (p) (void)hipFree(p);
     s->en.release();
     if (s->inv_host) (void)hipHostFree(s->inv_host);
@@ -64,25 +73,42 @@ eifp_status alloc(void** p, size_t n, long long* bytes) {
     return EIFP_OK;
 }
 
-// Write both descriptors for step size tau.  The copy is synchronous with respect to
-// the host buffer (the stream is drained first), so it only happens when tau changes.
-eifp_status upload_desc(eifp_solver* s, double tau) {
+// Write the descriptors for step size tau and jump span `span`.  The copy is
+// synchronous with respect to the host buffer (the stream is drained first), so it
+// only happens when tau or the span changes.
+eifp_status upload_desc(eifp_solver* s, double tau, double span) {
     const Grid3& g = s->en.g;
-    DescImage d{s->state, s->state, s->partials, s->inv_dev,
-                make_params(g.nx, g.ny, g.nz, s->dom, s->mu, s->eps, tau)};
-    s->desc_host[0] = d;
-    d.work = s->scratch;
-    d.pp = make_params(g.nx, g.ny, g.nz, s->dom, s->mu, s->eps, 0.0);
-    s->desc_host[1] = d;
+    const PropParams p0 = make_params(g.nx, g.ny, g.nz, s->dom, s->mu, s->eps, 0.0);
+    s->desc_host[0] = DescImage{s->state, s->state, s->partials, s->inv_dev, nullptr,
+                                make_params(g.nx, g.ny, g.nz, s->dom, s->mu, s->eps, tau)};
+    s->desc_host[1] = DescImage{s->state, s->scratch, s->partials, s->inv_dev, nullptr, p0};
+    s->desc_host[2] = DescImage{s->state, s->anchor, s->partials, s->inv_dev, nullptr, p0};
+    s->desc_host[3] = DescImage{s->state, s->state, s->partials, s->inv_dev, s->anchor,
+                                make_params(g.nx, g.ny, g.nz, s->dom, s->mu, s->eps, span)};
     EIFP_HIP_TRY(hipStreamSynchronize(s->stream));
     EIFP_HIP_TRY(hipMemcpyAsync(s->desc_dev, s->desc_host, sizeof s->desc_host, hipMemcpyHostToDevice, s->stream));
     EIFP_HIP_TRY(hipStreamSynchronize(s->stream));
     s->desc_tau = tau;
+    s->jump_span = span;
     return EIFP_OK;
 }
 
-const void* step_desc(const eifp_solver* s) { return s->desc_dev; }
-const void* fwd_desc(const eifp_solver* s) { return (const char*)s->desc_dev + sizeof(DescImage); }
+const void* desc_at(const eifp_solver* s, int i) { return (const char*)s->desc_dev + i * sizeof(DescImage); }
+const void* step_desc(const eifp_solver* s) { return desc_at(s, 0); }
+const void* fwd_desc(const eifp_solver* s) { return desc_at(s, 1); }
+
+// Store the spectrum of the current state as the anchor (time t).
+eifp_status make_anchor(eifp_solver* s) {
+    eifp_status st;
+    if (!s->anchor) {
+        if ((st = alloc(&s->anchor, s->en.state_bytes(), &s->bytes))) return st;
+        if ((st = upload_desc(s, s->desc_tau, s->jump_span))) return st;
+    }
+    if ((st = s->en.forward_spectrum(desc_at(s, 2), 1, s->stream))) return st;
+    s->anchor_valid = true;
+    s->t_anchor = s->t;
+    return EIFP_OK;
+}
 
 }  // namespace
 
@@ -135,9 +161,9 @@ eifp_status eifp_init(eifp_solver** out, int nx, int ny, int nz, const eifp_doma
     INIT_TRY(alloc(&s->scratch, sb, &s->bytes));
     INIT_TRY(alloc((void**)&s->partials, s->en.partial_bytes(), &s->bytes));
     INIT_TRY(alloc((void**)&s->inv_dev, 8 * sizeof(double), &s->bytes));
-    INIT_TRY(alloc(&s->desc_dev, 2 * sizeof(DescImage), &s->bytes));
+    INIT_TRY(alloc(&s->desc_dev, sizeof s->desc_host, &s->bytes));
     INIT_HIP(hipHostMalloc((void**)&s->inv_host, 8 * sizeof(double), hipHostMallocDefault));
-    INIT_TRY(upload_desc(s, 0.0));
+    INIT_TRY(upload_desc(s, 0.0, 0.0));
     // upload: FP64 directly; FP32 through the scratch buffer (3 ns doubles = 6 ns floats)
     const size_t half = (size_t)3 * ns * sizeof(double);
     if (prec == EIFP_FP64) {
@@ -169,7 +195,8 @@ static eifp_status step_impl(eifp_solver* s, double tau, long long nsteps, doubl
             for (int i = 0; i < 6; ++i) pass_ms[i] = 0.0;
         return EIFP_OK;
     }
-    if (tau != s->desc_tau && (st = upload_desc(s, tau))) return st;
+    if (tau != s->desc_tau && (st = upload_desc(s, tau, s->jump_span))) return st;
+    s->anchor_valid = false;  // the state no longer follows from the anchor
     if (pass_ms) {
         const size_t need = (size_t)7 * (size_t)nsteps;
         while (s->events.size() < need) {
@@ -201,6 +228,31 @@ static eifp_status step_impl(eifp_solver* s, double tau, long long nsteps, doubl
 }
 
 eifp_status eifp_step(eifp_solver* s, double tau, long long nsteps) { return step_impl(s, tau, nsteps, nullptr); }
+
+eifp_status eifp_anchor(eifp_solver* s) {
+    clear_error();
+    if (!s) return fail(EIFP_ERR_INVALID_ARG, "solver is NULL");
+    return make_anchor(s);
+}
+
+eifp_status eifp_jump(eifp_solver* s, double tau, long long nsteps) {
+    clear_error();
+    if (!s) return fail(EIFP_ERR_INVALID_ARG, "solver is NULL");
+    eifp_status st;
+    if ((st = validate_tau(tau))) return st;
+    if (nsteps < 0) return fail(EIFP_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if (nsteps == 0) return EIFP_OK;
+    if (!s->anchor_valid && (st = make_anchor(s))) return st;
+    const double t_new = s->t + tau * (double)nsteps;
+    const double span = t_new - s->t_anchor;
+    if (!std::isfinite(span)) return fail(EIFP_ERR_INVALID_ARG, "time span is not finite");
+    if (span != s->jump_span && (st = upload_desc(s, s->desc_tau, span))) return st;
+    if ((st = s->en.jump(desc_at(s, 3), 1, s->stream))) return st;
+    s->t = t_new;
+    s->steps += nsteps;
+    s->inv_current = true;
+    return EIFP_OK;
+}
 
 eifp_status eifp_step_timed(eifp_solver* s, double tau, long long nsteps, double* pass_ms) {
     if (!pass_ms) return fail(EIFP_ERR_INVALID_ARG, "pass_ms is NULL");

@@ -102,6 +102,8 @@ SIGNATURES = {
                                  ctypes.POINTER(eifp_domain), ctypes.c_double, ctypes.c_double,
                                  ctypes.c_int, _DP, _DP, _VP]),
     "eifp_step": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_longlong]),
+    "eifp_anchor": (ctypes.c_int, [_VP]),
+    "eifp_jump": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_longlong]),
     "eifp_step_timed": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_longlong, _DP]),
     "eifp_invariants": (ctypes.c_int, [_VP, ctypes.POINTER(eifp_invariant_set)]),
     "eifp_fields": (ctypes.c_int, [_VP, _DP, _DP]),
@@ -203,6 +205,14 @@ def eifp_step(handle, tau, nsteps=1):
     _check(load().eifp_step(handle, float(tau), int(nsteps)), "eifp_step")
 
 
+def eifp_anchor(handle):
+    _check(load().eifp_anchor(handle), "eifp_anchor")
+
+
+def eifp_jump(handle, tau, nsteps=1):
+    _check(load().eifp_jump(handle, float(tau), int(nsteps)), "eifp_jump")
+
+
 def eifp_step_timed(handle, tau, nsteps=1) -> dict:
     out = np.zeros(6)
     _check(load().eifp_step_timed(handle, float(tau), int(nsteps), _dp(out)), "eifp_step_timed")
@@ -275,6 +285,14 @@ class Solver:
 
     def step(self, tau, nsteps=1):
         eifp_step(self.handle, tau, nsteps)
+        return self
+
+    def anchor(self):
+        eifp_anchor(self.handle)
+        return self
+
+    def jump(self, tau, nsteps=1):
+        eifp_jump(self.handle, tau, nsteps)
         return self
 
     def step_timed(self, tau, nsteps=1) -> dict:
