@@ -178,7 +178,11 @@ enum {
 enum {
     EIFP_REQ_KEEP_RESULT = 1, /* keep the final fields on the device after completion,
                                  for eifp_server_fields, until eifp_server_release */
-    EIFP_REQ_NO_SNAPSHOT = 2  /* no device-side field snapshot at each output */
+    EIFP_REQ_NO_SNAPSHOT = 2, /* no device-side field snapshot at each output */
+    EIFP_REQ_ANCHORED = 4     /* compute each output by a jump from the stored spectrum of
+                                 the initial state (as eifp_jump) instead of stepping:
+                                 one propagation and inverse transform per output, no
+                                 error accumulation; costs one more state-sized buffer */
 };
 
 /* One solve (Alg. 2 on Omega = dom with constants mu, eps, step tau, nsteps steps). */
@@ -234,7 +238,8 @@ typedef struct {
 eifp_status eifp_server_create(eifp_server **out, long long hbm_budget_bytes, int max_batch, int flags);
 
 /* Device bytes one request of this shape holds while admitted: its state, plus an equal
- * snapshot buffer unless EIFP_REQ_NO_SNAPSHOT.  0 for an invalid shape or precision. */
+ * snapshot buffer unless EIFP_REQ_NO_SNAPSHOT, plus an equal spectrum buffer with
+ * EIFP_REQ_ANCHORED.  0 for an invalid shape or precision. */
 long long eifp_server_footprint(int nx, int ny, int nz, eifp_precision prec, int flags);
 
 /* Queue a solve; the fields are copied before returning.  *req_id receives its id.

@@ -44,10 +44,15 @@ constexpr double kModelBw = 4.0e12;      // bytes/s, first guess of a step's tim
 
 struct Key {
     int nx, ny, nz, prec;
+    int anchored;  // members advance by jumps from their anchored spectra
     bool operator<(const Key& o) const {
-        return std::tie(nx, ny, nz, prec) < std::tie(o.nx, o.ny, o.nz, o.prec);
+        return std::tie(nx, ny, nz, prec, anchored) < std::tie(o.nx, o.ny, o.nz, o.prec, o.anchored);
     }
 };
+
+Key key_of(const eifp_request& rq) {
+    return Key{rq.nx, rq.ny, rq.nz, (int)rq.prec, (rq.flags & EIFP_REQ_ANCHORED) ? 1 : 0};
+}
 
 struct Group;
 
@@ -61,6 +66,8 @@ struct Req {
     long long state_bytes = 0, bytes = 0;
     void* state = nullptr;
     void* snap = nullptr;
+    void* spec = nullptr;  // anchored spectrum (anchored requests)
+    bool anchored = false;  // spec holds the spectrum of the initial state
     Group* g = nullptr;
     long long done = 0;    // steps completed and observed
     long long target = 0;  // steps done once the in-flight chunk completes
@@ -105,13 +112,14 @@ int nparts_of(const Key& k) {
 long long group_bytes_of(const Key& k, int max_batch) {
     const long long ts = k.prec == EIFP_FP64 ? 8 : 4;
     const long long np = nparts_of(k);
-    return (long long)max_batch * (np * INV_NPART * 8 + 8 * 8 + (long long)sizeof(DescImage)) +
+    // partial and invariant slots, two descriptor regions (jumps and anchoring), tables
+    return (long long)max_batch * (np * INV_NPART * 8 + 8 * 8 + 2 * (long long)sizeof(DescImage)) +
            2 * ts * (k.nx + k.ny + k.nz);
 }
 
 long long footprint_of(int nx, int ny, int nz, int prec, int flags) {
     const long long sb = state_bytes_of(nx, ny, nz, prec);
-    return (flags & EIFP_REQ_NO_SNAPSHOT) ? sb : 2 * sb;
+    return sb * (1 + ((flags & EIFP_REQ_NO_SNAPSHOT) ? 0 : 1) + ((flags & EIFP_REQ_ANCHORED) ? 1 : 0));
 }
 
 double pct(std::vector<double> v, double q) {
@@ -180,11 +188,11 @@ eifp_status group_alloc(Group* g, int max_batch) {
     g->nparts = g->en.nparts;
     const size_t pb = (size_t)max_batch * g->nparts * INV_NPART * sizeof(double);
     if (hipMalloc((void**)&g->partials, pb) != hipSuccess || hipMalloc((void**)&g->inv_dev, max_batch * 64) != hipSuccess ||
-        hipMalloc(&g->desc_dev, max_batch * sizeof(DescImage)) != hipSuccess) {
+        hipMalloc(&g->desc_dev, 2 * max_batch * sizeof(DescImage)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(EIFP_ERR_OUT_OF_MEMORY, "batch table allocation failed");
     }
-    EIFP_HIP_TRY(hipHostMalloc((void**)&g->desc_host, max_batch * sizeof(DescImage), hipHostMallocDefault));
+    EIFP_HIP_TRY(hipHostMalloc((void**)&g->desc_host, 2 * max_batch * sizeof(DescImage), hipHostMallocDefault));
     EIFP_HIP_TRY(hipHostMalloc((void**)&g->inv_host, max_batch * 64, hipHostMallocDefault));
     return EIFP_OK;
 }
@@ -193,8 +201,9 @@ void req_free_device(eifp_server* sv, Req* r) {
     if (!sv->dry) {
         if (r->state) (void)hipFree(r->state);
         if (r->snap) (void)hipFree(r->snap);
+        if (r->spec) (void)hipFree(r->spec);
     }
-    r->state = r->snap = nullptr;
+    r->state = r->snap = r->spec = nullptr;
     sv->used -= r->bytes;
     r->bytes = 0;
 }
@@ -249,11 +258,12 @@ void retire(eifp_server* sv, Req* r, bool ok) {
         // keep the final state; the snapshot buffer goes back to the budget
         r->kept = true;
         if (r->snap && !sv->dry) (void)hipFree(r->snap);
-        if (!(r->rq.flags & EIFP_REQ_NO_SNAPSHOT)) {
-            sv->used -= r->state_bytes;
-            r->bytes -= r->state_bytes;
-        }
-        r->snap = nullptr;
+        if (r->spec && !sv->dry) (void)hipFree(r->spec);
+        const long long extra = (long long)(!(r->rq.flags & EIFP_REQ_NO_SNAPSHOT)) +
+                                (long long)((r->rq.flags & EIFP_REQ_ANCHORED) != 0);
+        sv->used -= extra * r->state_bytes;
+        r->bytes -= extra * r->state_bytes;
+        r->snap = r->spec = nullptr;
         r->has_snap = false;
     } else {
         req_free_device(sv, r);
@@ -300,10 +310,12 @@ eifp_status admit_one(eifp_server* sv, Req* r, Group* g) {
     const long long fp = footprint_of(r->rq.nx, r->rq.ny, r->rq.nz, r->rq.prec, r->rq.flags);
     if (!sv->dry) {
         if (hipMalloc(&r->state, r->state_bytes) != hipSuccess ||
-            (!(r->rq.flags & EIFP_REQ_NO_SNAPSHOT) && hipMalloc(&r->snap, r->state_bytes) != hipSuccess)) {
+            (!(r->rq.flags & EIFP_REQ_NO_SNAPSHOT) && hipMalloc(&r->snap, r->state_bytes) != hipSuccess) ||
+            ((r->rq.flags & EIFP_REQ_ANCHORED) && hipMalloc(&r->spec, r->state_bytes) != hipSuccess)) {
             (void)hipGetLastError();
-            if (r->state) (void)hipFree(r->state);
-            r->state = nullptr;
+            for (void* p : {r->state, r->snap, r->spec})
+                if (p) (void)hipFree(p);
+            r->state = r->snap = r->spec = nullptr;
             return fail(EIFP_ERR_OUT_OF_MEMORY, "request allocation failed");
         }
         const void* src = r->rq.prec == EIFP_FP64 ? (const void*)r->host64.data() : (const void*)r->host32.data();
@@ -328,7 +340,7 @@ bool admit(eifp_server* sv) {
     for (auto it = sv->pending.begin(); it != sv->pending.end();) {
         Req* r = *it;
         if ((sv->flags & EIFP_SERVER_SERIAL) && sv->running > 0) break;
-        const Key k{r->rq.nx, r->rq.ny, r->rq.nz, r->rq.prec};
+        const Key k = key_of(r->rq);
         auto git = sv->groups.find(k);
         Group* g = git == sv->groups.end() ? nullptr : git->second.get();
         const long long need = footprint_of(k.nx, k.ny, k.nz, k.prec, r->rq.flags) +
@@ -346,7 +358,7 @@ bool admit(eifp_server* sv) {
                 r->done = 0;
                 push_event(sv, r, EIFP_EV_ERROR, st, nullptr);
                 sv->failed++;
-                if (r->state || r->snap) req_free_device(sv, r);
+                if (r->state || r->snap || r->spec) req_free_device(sv, r);
                 sv->reqs.erase(r->id);
             }
             continue;
@@ -381,6 +393,56 @@ eifp_status capture_step_graph(Group* g, int nm, bool want_inv, hipGraphExec_t* 
     const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ei != hipSuccess) return fail(EIFP_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ei));
+    return EIFP_OK;
+}
+
+// A chunk of a jump group: members not yet anchored get their spectrum stored (forward
+// transform into spec, through the second descriptor region), then every member jumps
+// from its anchor to its own next output point (descriptor region one, rewritten each
+// chunk since the time spans change).  Every jump ends at an output point, so the
+// invariants are always reduced.
+eifp_status launch_jump_chunk(eifp_server* sv, Group* g) {
+    const int nm = (int)g->members.size();
+    const Grid3& gg = g->en.g;
+    if (!sv->dry) {
+        int na = 0;
+        for (Req* r : g->members)
+            if (!r->anchored) {
+                const PropParams p0 = make_params(gg.nx, gg.ny, gg.nz, r->rq.dom, r->rq.mu, r->rq.eps, 0.0);
+                g->desc_host[sv->max_batch + na++] = DescImage{r->state, r->spec, nullptr, nullptr, nullptr, p0};
+            }
+        for (int i = 0; i < nm; ++i) {
+            Req* r = g->members[i];
+            const double span = r->rq.tau * (double)next_boundary(r);
+            g->desc_host[i] = DescImage{r->state, r->state, g->partials + (size_t)i * g->nparts * INV_NPART,
+                                        g->inv_dev + (size_t)i * 8, r->spec,
+                                        make_params(gg.nx, gg.ny, gg.nz, r->rq.dom, r->rq.mu, r->rq.eps, span)};
+        }
+        EIFP_HIP_TRY(hipMemcpyAsync(g->desc_dev, g->desc_host, (size_t)(sv->max_batch + na) * sizeof(DescImage),
+                                    hipMemcpyHostToDevice, g->st));
+        EIFP_HIP_TRY(hipEventRecord(g->ev0, g->st));
+        eifp_status st;
+        if (na && (st = g->en.forward_spectrum((const char*)g->desc_dev + sv->max_batch * sizeof(DescImage), na, g->st)))
+            return st;
+        if ((st = g->en.jump(g->desc_dev, nm, g->st, true))) return st;
+        for (Req* r : g->members)
+            if (r->snap && next_boundary(r) < r->rq.nsteps)
+                EIFP_HIP_TRY(hipMemcpyAsync(r->snap, r->state, r->state_bytes, hipMemcpyDeviceToDevice, g->st));
+        EIFP_HIP_TRY(hipMemcpyAsync(g->inv_host, g->inv_dev, (size_t)nm * 64, hipMemcpyDeviceToHost, g->st));
+        EIFP_HIP_TRY(hipEventRecord(g->ev1, g->st));
+    }
+    long long kmax = 0;
+    for (Req* r : g->members) {
+        r->anchored = true;
+        r->target = next_boundary(r);
+        kmax = std::max(kmax, r->target - r->done);
+    }
+    g->dirty = false;
+    g->k = (int)std::min<long long>(kmax, 1 << 30);
+    g->nm_flight = nm;
+    g->in_flight = true;
+    sv->chunks++;
+    sv->batch_sum += nm;
     return EIFP_OK;
 }
 
@@ -452,7 +514,8 @@ bool poll_group(eifp_server* sv, Group* g) {
             return true;
         }
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, g->ev0, g->ev1) == hipSuccess && g->k > 0 && g->nm_flight > 0) {
+        if (!g->key.anchored && hipEventElapsedTime(&ms, g->ev0, g->ev1) == hipSuccess && g->k > 0 &&
+            g->nm_flight > 0) {
             const double m = (double)ms / ((double)g->k * g->nm_flight);
             g->ms_per_member_step = g->ms_per_member_step > 0 ? 0.5 * (g->ms_per_member_step + m) : m;
         }
@@ -513,7 +576,7 @@ void scheduler(eifp_server* sv) {
         for (auto& kv : sv->groups) {
             Group* g = kv.second.get();
             if (!g->in_flight && !g->members.empty() && g->readers == 0) {
-                const eifp_status st = launch_chunk(sv, g);
+                const eifp_status st = g->key.anchored ? launch_jump_chunk(sv, g) : launch_chunk(sv, g);
                 if (st) fail_group(sv, g, st);
                 progress = true;
             }
@@ -603,7 +666,7 @@ eifp_status eifp_server_submit(eifp_server* sv, const eifp_request* rq, long lon
     if (!sv || !req_id) return fail(EIFP_ERR_INVALID_ARG, "NULL argument");
     eifp_status st = validate_request(rq);
     if (st) return st;
-    const Key k{rq->nx, rq->ny, rq->nz, (int)rq->prec};
+    const Key k = key_of(*rq);
     const long long need = footprint_of(k.nx, k.ny, k.nz, k.prec, rq->flags) + group_bytes_of(k, sv->max_batch);
     if (need > sv->budget)
         return fail(EIFP_ERR_OUT_OF_MEMORY, "request needs %lld bytes, budget is %lld", need, sv->budget);

@@ -52,6 +52,7 @@ EIFP_SERVER_NO_GRAPHS = 2
 EIFP_SERVER_SERIAL = 4
 EIFP_REQ_KEEP_RESULT = 1
 EIFP_REQ_NO_SNAPSHOT = 2
+EIFP_REQ_ANCHORED = 4
 EIFP_EV_OUTPUT = 0
 EIFP_EV_DONE = 1
 EIFP_EV_ERROR = 2

@@ -94,7 +94,7 @@ def service_time(r, step_s, prec=None):
 
 
 def replay(reqs, pools, budget: int, max_batch: int = 32, flags: int = 0, force_prec=None, progress=None,
-           step_s=None):
+           step_s=None, req_flags: int = 0):
     """Submit each request at its arrival time (relative to the start) from a thread of
     its own, collect every event, and return the summary."""
     sv = eifp.Server(budget, max_batch, flags)
@@ -112,7 +112,7 @@ def replay(reqs, pools, budget: int, max_batch: int = 32, flags: int = 0, force_
             H, E = pools[(r["shape"], r["pool_index"])]
             try:
                 sv.submit(H, E, r["domain"], r["mu"], r["eps"], r["tau"], r["nsteps"], r["cadence"],
-                          force_prec or r["prec"], r["tag"], 0)
+                          force_prec or r["prec"], r["tag"], req_flags)
             except Exception as ex:  # recorded, reported below
                 errors.append((r["tag"], str(ex)))
             submit_lag.append(time.perf_counter() - t0 - r["arrival"])
@@ -171,14 +171,17 @@ def run_stream(n_requests=64, load=0.8, pool=1, budget=24 * 10 ** 9, max_batch=3
            "rate_per_s": None if burst else rate, "mean_service_s": mean_service, "pool": pool,
            "max_steps": max_steps, "budget_bytes": budget, "max_batch": max_batch,
            "step_ms": {f"{s[0]}x{s[1]}x{s[2]}_{p}": round(v * 1e3, 4) for (s, p), v in sorted(step_s.items())}}
-    settings = {"batched": (max_batch, 0, None), "batched_no_graphs": (max_batch, eifp.EIFP_SERVER_NO_GRAPHS, None),
-                "serial_own": (1, eifp.EIFP_SERVER_SERIAL, None),
-                "serial_fp64": (1, eifp.EIFP_SERVER_SERIAL, "fp64")}
+    # mode: (max batch, server flags, forced precision, request flags)
+    settings = {"batched": (max_batch, 0, None, 0),
+                "batched_no_graphs": (max_batch, eifp.EIFP_SERVER_NO_GRAPHS, None, 0),
+                "serial_own": (1, eifp.EIFP_SERVER_SERIAL, None, 0),
+                "serial_fp64": (1, eifp.EIFP_SERVER_SERIAL, "fp64", 0),
+                "anchored": (max_batch, 0, None, eifp.EIFP_REQ_ANCHORED)}
     for mode in modes:
-        mb, fl, fp = settings[mode]
+        mb, fl, fp, rf = settings[mode]
         if progress:
             progress(f"{mode}: {n_requests} requests" + (" (burst)" if burst else f" at {rate:.2f}/s"))
-        out[mode] = replay(reqs, pools, budget, mb, fl, fp, progress=progress, step_s=step_s)
+        out[mode] = replay(reqs, pools, budget, mb, fl, fp, progress=progress, step_s=step_s, req_flags=rf)
     return out
 
 
@@ -191,7 +194,7 @@ def main():
     ap.add_argument("--max-batch", type=int, default=32)
     ap.add_argument("--max-steps", type=int, default=5000)
     ap.add_argument("--modes", default="batched,serial_own,serial_fp64",
-                    help="comma list of batched, batched_no_graphs, serial_own, serial_fp64")
+                    help="comma list of batched, batched_no_graphs, serial_own, serial_fp64, anchored")
     ap.add_argument("--burst", action="store_true", help="every request arrives at t = 0")
     a = ap.parse_args()
     res = run_stream(a.requests, a.load, a.pool, int(a.budget_gb * 1e9), a.max_batch, tuple(a.modes.split(",")),

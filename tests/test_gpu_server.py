@@ -174,3 +174,46 @@ def test_serial_mode_and_stats():
     mix, _ = run(m, MIX[:4])
     for i in res:
         assert np.array_equal(res[i][0], mix[i][0]), i
+
+
+def test_anchored_requests_match_solver_jumps_and_oracle():
+    # anchored requests: every output is one jump from the stored initial spectrum; the
+    # server's result equals the solver's eifp_jump bit for bit, and the oracle's single
+    # step of nsteps * tau within tolerance (FP32 too, with no growth in nsteps)
+    m = eifp()
+    cases = [c[:5] + (c[5] * 20,) + c[6:] for c in MIX]  # 20x the steps: error must not grow
+    res = {}
+    with m.Server(BUDGET, 8) as sv:
+        ids = {}
+        for i, c in enumerate(cases):
+            shape, dom, mu, eps, tau, nsteps, cad, prec, _ = c
+            H, E = fields_of(c)
+            ids[sv.submit(H, E, dom, mu, eps, tau, nsteps, cad, prec, i,
+                          m.EIFP_REQ_KEEP_RESULT | m.EIFP_REQ_ANCHORED)] = i
+        sv.drain(60000)
+        evs = []
+        while True:
+            got = sv.poll(4096, 0)
+            if not got:
+                break
+            evs += got
+        st = sv.stats()
+        assert st["failed"] == 0 and st["completed"] == len(cases)
+        for rid, i in ids.items():
+            res[i] = sv.fields(rid, cases[i][0])
+            outs = [e["step"] for e in evs if e["req_id"] == rid]
+            cad, n = cases[i][6], cases[i][5]
+            assert outs == ([s for s in range(cad, n, cad)] if cad else []) + [n]
+            sv.release(rid)
+    for i, c in enumerate(cases):
+        shape, dom, mu, eps, tau, nsteps, cad, prec, _ = c
+        H, E = fields_of(c)
+        with m.Solver(H, E, dom, mu, eps, prec) as s:
+            s.jump(tau, nsteps)
+            Hs, Es = s.fields()
+        Hg, Eg, step = res[i]
+        assert step == nsteps
+        assert np.array_equal(Hg, Hs) and np.array_equal(Eg, Es), i
+        Ho, Eo, _ = orc.step(H, E, dom, mu, eps, tau * nsteps, 1)
+        tol = FP64_TOL if prec == "fp64" else FP32_TOL
+        assert energy_rel_error(Hg, Eg, Ho, Eo, mu, eps) <= tol, (i, prec)

@@ -186,3 +186,17 @@ def test_mixed_stream_batches_same_shapes():
     assert st["completed"] == n_req and st["failed"] == 0
     assert sum(e["kind"] == "done" for e in evs) == n_req
     assert st["bytes_in_use"] >= 0
+
+
+def test_anchored_requests_in_dry_run():
+    m = eifp()
+    fp = m.eifp_server_footprint(16, 16, 16, "fp64", m.EIFP_REQ_ANCHORED)
+    assert fp == 3 * 6 * 16 ** 3 * 8
+    with m.Server(1 << 30, 4, m.EIFP_SERVER_DRY_RUN) as sv:
+        a = sv.submit(zeros(16), zeros(16), CUBE, nsteps=1000, cadence=250, flags=m.EIFP_REQ_ANCHORED, tag=1)
+        b = sv.submit(zeros(16), zeros(16), CUBE, nsteps=1000, cadence=250, tag=2)
+        evs = events_by_request(drain_events(sv))
+        st = sv.stats()
+    assert [e["step"] for e in evs[a]] == [250, 500, 750, 1000]
+    assert [e["step"] for e in evs[b]] == [250, 500, 750, 1000]
+    assert st["completed"] == 2
