@@ -64,6 +64,20 @@ typedef struct {
     double div_e_l2;      /* ||div~(eps E)||_N                               (Thm 4.6) */
 } eifp_invariant_set;
 
+/* Further conserved quantities of Thms 4.1 and 4.3 for the current state, computed on
+ * the device from the spectrum (Parseval), with the time derivatives taken from the
+ * semi-discrete system (2.4): d/dt H = -(1/mu) D E, d/dt E = (1/eps) D H.  The
+ * remaining ones of those theorems are identities: E5 = E6 = 0 (D_k is skew) and
+ * M2 = -M1 (Thm 4.4). */
+typedef struct {
+    double t;             /* as eifp_invariant_set */
+    long long steps_done;
+    double e2;            /* E2 = mu/2 <H_t,H_t>_N + eps/2 <E_t,E_t>_N              (Thm 4.1) */
+    double e3[3];         /* E3 = mu/2 <D_k H,D_k H>_N + eps/2 <D_k E,D_k E>_N, k = x,y,z */
+    double e4[3];         /* E4 = the same on H_t, E_t                                      */
+    double h2;            /* H2 = <H_t,D H_t>_N/(2 eps) + <E_t,D E_t>_N/(2 mu)       (Thm 4.3) */
+} eifp_invariant_ext_set;
+
 /* Create a solver and load the initial values (Def. 2.3 step 2).
  *   out       receives the handle (set to NULL on failure)
  *   nx,ny,nz  grid sizes (see above)
@@ -115,6 +129,11 @@ eifp_status eifp_step_timed(eifp_solver *s, double tau, long long nsteps, double
  * state (the state is not modified).  Errors: INVALID_ARG (NULL), NONFINITE (a
  * non-finite invariant: the state holds NaN/Inf), DEVICE. */
 eifp_status eifp_invariants(eifp_solver *s, eifp_invariant_set *out);
+
+/* Extended invariants (eifp_invariant_ext_set) of the current state, by a forward-only
+ * transform of the state (not modified).  Synchronises.  Errors: INVALID_ARG (NULL),
+ * NONFINITE, DEVICE. */
+eifp_status eifp_invariants_ext(eifp_solver *s, eifp_invariant_ext_set *out);
 
 /* Copy the current fields to caller-owned host arrays of 3*nx*ny*nz doubles each,
  * layout [3][nz][ny][nx] (Def. 2.3 step 4 output).  FP32 state is widened exactly.

@@ -59,10 +59,12 @@ struct Engine {
     eifp_status init(int nx, int ny, int nz, eifp_precision p);
     void release();
     size_t state_bytes() const { return (size_t)6 * (size_t)ns * tsize; }
-    size_t partial_bytes() const { return (size_t)nparts * INV_NPART * sizeof(double); }
+    // room for the extended record (INV_XPART doubles per workgroup)
+    size_t partial_bytes() const { return (size_t)nparts * INV_XPART * sizeof(double); }
 
     // One step (mode Z_STEP: x, z, fused y, z^-1, x^-1, finalize) or a forward-only
-    // evaluation of the invariants (mode Z_FORWARD: state -> work, nothing stored back),
+    // evaluation of the invariants (mode Z_FORWARD, or Z_FORWARD_EXT for the extended
+    // record: state -> work, nothing stored back),
     // for nm members described by the device array md.  ev: 7 events recorded around
     // the kernels (or null).  want_inv = false skips the invariant partial sums and the
     // finalize (a step between output points).

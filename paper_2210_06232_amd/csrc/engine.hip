@@ -67,7 +67,8 @@ eifp_status run_passes(const Engine& en, int mode, const void* md, int nm, hipSt
         EIFP_HIP_TRY(hipEventRecord(ev[4], st));
         EIFP_HIP_TRY(hipEventRecord(ev[5], st));
     }
-    if (want_inv && (rc = launch_finalize<T>(md, nm, en.nparts, st))) return rc_to_status(rc, "finalize");
+    if (want_inv && (rc = launch_finalize<T>(md, nm, en.nparts, st, mode == Z_FORWARD_EXT)))
+        return rc_to_status(rc, "finalize");
     if (ev) EIFP_HIP_TRY(hipEventRecord(ev[6], st));
     return EIFP_OK;
 }

@@ -52,8 +52,10 @@ struct MemberDesc {
     PropParams pp;
 };
 
-// invariant partial sums per workgroup (all in FP64)
+// invariant partial sums per workgroup (all in FP64); the extended record adds the
+// energies of the derivatives and the second helicity (Thms 4.1 and 4.3)
 enum { INV_E1 = 0, INV_H1, INV_M1X, INV_M1Y, INV_M1Z, INV_DIVH, INV_DIVE, INV_NPART = 8 };
+enum { INV_E2 = 8, INV_E3X, INV_E3Y, INV_E3Z, INV_E4X, INV_E4Y, INV_E4Z, INV_H2, INV_XPART = 16 };
 
 // Omega_w[m] of Sec. 2.3: nu m for m < n/2, 0 at the Nyquist index, nu (m - n) above.
 __device__ __forceinline__ double omega(int m, int n, double nu) {
@@ -239,7 +241,9 @@ k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, l
 // Z_FORWARD: forward, partials only (invariants of the state; memory untouched).
 // Z_JUMP: read the anchored spectrum (all three forward transforms already done),
 // propagate by the member's tau, partials, inverse along the fused axis into work.
-enum ZMode { Z_STEP = 0, Z_FORWARD = 1, Z_JUMP = 2 };
+// Z_FORWARD_EXT: as Z_FORWARD with the extended invariant record.
+enum ZMode { Z_STEP = 0, Z_FORWARD = 1, Z_JUMP = 2, Z_FORWARD_EXT = 3 };
+template <int MODE> struct NQ { static constexpr int value = MODE == Z_FORWARD_EXT ? INV_XPART : INV_NPART; };
 
 template <typename T>
 __device__ __forceinline__ double dreal(T a) { return (double)a; }
@@ -247,8 +251,8 @@ __device__ __forceinline__ double dreal(T a) { return (double)a; }
 // Accumulate the weighted spectral sums of one mode.  h, e are the six propagated
 // coefficients already multiplied by 1/N_S, so sums of their products are the
 // discrete inner products of Sec. 4 (Parseval) with no further scaling.
-template <typename T>
-__device__ __forceinline__ void accumulate_invariants(double (&acc)[INV_NPART], double w, double bx, double by, double bz,
+template <int Q, typename T>
+__device__ __forceinline__ void accumulate_invariants(double (&acc)[Q], double w, double bx, double by, double bz,
                                                       const cpx<T>* h, const cpx<T>* e, const PropParams& pp) {
     const double mu = pp.mu, eps = pp.eps;
     const double hr[3] = {dreal(h[0].x), dreal(h[1].x), dreal(h[2].x)};
@@ -279,13 +283,31 @@ __device__ __forceinline__ void accumulate_invariants(double (&acc)[INV_NPART], 
     const double der = bx * er[0] + by * er[1] + bz * er[2], dei = bx * ei[0] + by * ei[1] + bz * ei[2];
     acc[INV_DIVH] += w * mu * mu * (dhr * dhr + dhi * dhi);
     acc[INV_DIVE] += w * eps * eps * (der * der + dei * dei);
+    if constexpr (Q > INV_NPART) {
+        // time derivatives from the semi-discrete system: d/dt H^ = -(i/mu) b x E^,
+        // d/dt E^ = (i/eps) b x H^, with |b x U|^2 = |b|^2 |U|^2 - |b . U|^2 and
+        // b . (Re(b x A) x Re(b x B))-type helicity terms equal to |b|^2 times the
+        // undifferentiated ones
+        const double b2 = bx * bx + by * by + bz * bz;
+        const double en1 = 0.5 * (mu * h2 + eps * e2);
+        const double en2 = 0.5 * pp.inv_mu * (b2 * e2 - (der * der + dei * dei)) +
+                           0.5 * pp.inv_eps * (b2 * h2 - (dhr * dhr + dhi * dhi));
+        acc[INV_E2] += w * en2;
+        const double bk2[3] = {bx * bx, by * by, bz * bz};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            acc[INV_E3X + k] += w * bk2[k] * en1;
+            acc[INV_E4X + k] += w * bk2[k] * en2;
+        }
+        acc[INV_H2] += w * b2 * pp.inv_mu * pp.inv_eps * (hc * pp.inv_eps + ec * pp.inv_mu);
+    }
 }
 
-// Block-wide sum of INV_NPART doubles in a fixed order; thread 0 writes the partials.
-template <int NT>
-__device__ __forceinline__ void block_reduce_store(double (&acc)[INV_NPART], double* __restrict__ out, double* s_red) {
+// Block-wide sum of Q doubles in a fixed order; thread 0 writes the partials.
+template <int NT, int Q>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[Q], double* __restrict__ out, double* s_red) {
 #pragma unroll
-    for (int q = 0; q < INV_NPART; ++q) {
+    for (int q = 0; q < Q; ++q) {
         double a = acc[q];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
@@ -295,12 +317,12 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[INV_NPART], dou
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) {
 #pragma unroll
-        for (int q = 0; q < INV_NPART; ++q) s_red[wid * INV_NPART + q] = acc[q];
+        for (int q = 0; q < Q; ++q) s_red[wid * Q + q] = acc[q];
     }
     __syncthreads();
-    if (threadIdx.x < INV_NPART) {
+    if (threadIdx.x < Q) {
         double a = 0;
-        for (int w = 0; w < NW; ++w) a += s_red[w * INV_NPART + threadIdx.x];
+        for (int w = 0; w < NW; ++w) a += s_red[w * Q + threadIdx.x];
         out[threadIdx.x] = a;
     }
 }
@@ -376,7 +398,8 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
     constexpr int NZ = P::N, E = P::E, TT = P::T, NT = P::T * B;
     __shared__ T s_x[2 * 2 * NZ * zcol_pitch(B)];
     __shared__ cpx<T> s_tw[NZ];
-    __shared__ double s_red[((NT + 63) / 64) * INV_NPART];
+    constexpr int Q = NQ<MODE>::value;
+    __shared__ double s_red[((NT + 63) / 64) * Q];
     stage_table(s_tw, tw, NZ);
     const MemberDesc<T>& mem = md[blockIdx.z];
     const PropParams pp = mem.pp;
@@ -411,9 +434,9 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
 
     const double bx = col == 0 ? 0.0 : pp.nu[0] * (double)col;  // packed column: Omega_x = 0 at 0 and Nx/2
     const double bo = omega(o, n_outer, AXIS == 1 ? pp.nu[2] : pp.nu[1]);
-    double acc[INV_NPART];
+    double acc[Q];
 #pragma unroll
-    for (int q = 0; q < INV_NPART; ++q) acc[q] = 0.0;
+    for (int q = 0; q < Q; ++q) acc[q] = 0.0;
     const double w = col == 0 ? 1.0 : 2.0;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -425,7 +448,7 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
         const double bz = AXIS == 1 ? bo : bp;
         cpx<T> h[3] = {v[0][i], v[1][i], v[2][i]};
         cpx<T> e[3] = {v[3][i], v[4][i], v[5][i]};
-        if (MODE != Z_FORWARD) {
+        if (MODE == Z_STEP || MODE == Z_JUMP) {
             propagate_mode(h, e, bx, by, bz, pp);
         } else {
             const T s = (T)pp.inv_ns;
@@ -435,8 +458,8 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
                 e[q] = scale(e[q], s);
             }
         }
-        if (want_inv && active) accumulate_invariants(acc, w, bx, by, bz, h, e, pp);
-        if (MODE != Z_FORWARD) {
+        if (want_inv && active) accumulate_invariants<Q>(acc, w, bx, by, bz, h, e, pp);
+        if (MODE == Z_STEP || MODE == Z_JUMP) {
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 v[q][i] = h[q];
@@ -445,9 +468,8 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
         }
         if (EIFP_FUSED_SB & 2) __builtin_amdgcn_sched_barrier(0);  // one mode's temporaries live at a time
     }
-    if (want_inv)
-        block_reduce_store<NT>(acc, mem.partials + ((long)ty * gridDim.x + tx) * INV_NPART, s_red);
-    if (MODE != Z_FORWARD) {
+    if (want_inv) block_reduce_store<NT, Q>(acc, mem.partials + ((long)ty * gridDim.x + tx) * Q, s_red);
+    if (MODE == Z_STEP || MODE == Z_JUMP) {
         // inverse transform and store each component as soon as it is done; Z_FORWARD
         // leaves memory untouched
 #pragma unroll
@@ -467,31 +489,33 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
 // deterministic compensated finalize of the invariant partials
 // ---------------------------------------------------------------------------------
 // Grid: one block per member.  out (member's inv): [0] E1 [1] H1 [2..4] M1
-// [5] ||div~(mu H)||_N [6] ||div~(eps E)||_N
+// [5] ||div~(mu H)||_N [6] ||div~(eps E)||_N; extended record: [8] E2 [9..11] E3
+// [12..14] E4 [15] H2
 __device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
     const double t = s + x;
     c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
     s = t;
 }
 
-// Thread j sums records j, j + 1024, ... (each record: INV_NPART contiguous doubles)
-// with Neumaier compensation, then the 1024 (sum, compensation) pairs are combined by a
+// Thread j sums records j, j + 1024, ... (each record: Q contiguous doubles) with
+// Neumaier compensation, then the 1024 (sum, compensation) pairs are combined by a
 // fixed xor-butterfly inside each wave and a fixed loop over the 16 waves: the same
 // partials always give the same bits.
-template <typename T>
+template <typename T, int Q>
 __global__ void __launch_bounds__(1024) k_finalize(const MemberDesc<T>* __restrict__ md, int nparts) {
-    __shared__ double s_w[16][2 * INV_NPART];
+    __shared__ double s_w[16][2 * Q];
     const double* partials = md[blockIdx.x].partials;
-    double s[INV_NPART], c[INV_NPART];
+    double s[Q], c[Q];
 #pragma unroll
-    for (int q = 0; q < INV_NPART; ++q) s[q] = c[q] = 0.0;
+    for (int q = 0; q < Q; ++q) s[q] = c[q] = 0.0;
+#pragma unroll 2
     for (int j = threadIdx.x; j < nparts; j += 1024) {
-        const double* rec = partials + (long)j * INV_NPART;
+        const double* rec = partials + (long)j * Q;
 #pragma unroll
-        for (int q = 0; q < INV_NPART; ++q) neumaier_add(s[q], c[q], rec[q]);
+        for (int q = 0; q < Q; ++q) neumaier_add(s[q], c[q], rec[q]);
     }
 #pragma unroll
-    for (int q = 0; q < INV_NPART; ++q) {
+    for (int q = 0; q < Q; ++q) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             const double os = __shfl_xor(s[q], off, 64), oc = __shfl_xor(c[q], off, 64);
@@ -502,19 +526,19 @@ __global__ void __launch_bounds__(1024) k_finalize(const MemberDesc<T>* __restri
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) {
 #pragma unroll
-        for (int q = 0; q < INV_NPART; ++q) {
+        for (int q = 0; q < Q; ++q) {
             s_w[wid][q] = s[q];
-            s_w[wid][INV_NPART + q] = c[q];
+            s_w[wid][Q + q] = c[q];
         }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double res[INV_NPART];
+        double res[Q];
 #pragma unroll
-        for (int q = 0; q < INV_NPART; ++q) {
+        for (int q = 0; q < Q; ++q) {
             double a = 0.0, ca = 0.0;
             for (int w = 0; w < 16; ++w) {
-                ca += s_w[w][INV_NPART + q];
+                ca += s_w[w][Q + q];
                 neumaier_add(a, ca, s_w[w][q]);
             }
             res[q] = a + ca;
@@ -528,6 +552,8 @@ __global__ void __launch_bounds__(1024) k_finalize(const MemberDesc<T>* __restri
         out[5] = sqrt(res[INV_DIVH]);
         out[6] = sqrt(res[INV_DIVE]);
         out[7] = 0.0;
+#pragma unroll
+        for (int q = INV_NPART; q < Q; ++q) out[q] = res[q];
     }
 }
 

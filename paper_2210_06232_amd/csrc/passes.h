@@ -34,8 +34,9 @@ template <typename T>
 int launch_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const void* tw, hipStream_t st);
 
 // fused pass along `axis` on each member's work buffer: mode Z_STEP (forward, propagate,
-// partials, inverse, store), Z_FORWARD (forward, partials only; memory untouched) or
-// Z_JUMP (read the member's anchored spectrum, propagate, partials, inverse into work)
+// partials, inverse, store), Z_FORWARD (forward, partials only; memory untouched),
+// Z_FORWARD_EXT (the same with the extended invariant record) or Z_JUMP (read the
+// member's anchored spectrum, propagate, partials, inverse into work)
 template <typename T>
 int launch_fused(int mode, int axis, const Grid3& g, const void* md, int nm, const void* tw, int want_inv,
                  hipStream_t st);
@@ -44,8 +45,9 @@ int launch_fused(int mode, int axis, const Grid3& g, const void* md, int nm, con
 template <typename T>
 int fused_partial_count(int axis, const Grid3& g);
 
-// finalize each member's partials into its invariant record
+// finalize each member's partials into its invariant record (extended: the 16-value
+// record of Z_FORWARD_EXT)
 template <typename T>
-int launch_finalize(const void* md, int nm, int nparts, hipStream_t st);
+int launch_finalize(const void* md, int nm, int nparts, hipStream_t st, bool extended = false);
 
 }  // namespace eifp

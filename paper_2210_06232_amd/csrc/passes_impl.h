@@ -130,6 +130,7 @@ int run_fused(int mode, int axis, const Grid3& g, const void* md, int nm, const 
     if (mode == Z_STEP) run_fused_k<T, N, Z_STEP, AXIS_Y>(g, md, nm, tw, want_inv, st);
     else if (mode == Z_FORWARD) run_fused_k<T, N, Z_FORWARD, AXIS_Y>(g, md, nm, tw, want_inv, st);
     else if (mode == Z_JUMP) run_fused_k<T, N, Z_JUMP, AXIS_Y>(g, md, nm, tw, want_inv, st);
+    else if (mode == Z_FORWARD_EXT) run_fused_k<T, N, Z_FORWARD_EXT, AXIS_Y>(g, md, nm, tw, want_inv, st);
     else return kUnsupported;
     return check_launch();
 }
@@ -201,8 +202,11 @@ int fused_partial_count(int axis, const Grid3& g) {
 }
 
 template <typename T>
-int launch_finalize(const void* md, int nm, int nparts, hipStream_t st) {
-    hipLaunchKernelGGL((k_finalize<T>), dim3(nm), dim3(1024), 0, st, (const MemberDesc<T>*)md, nparts);
+int launch_finalize(const void* md, int nm, int nparts, hipStream_t st, bool extended) {
+    if (extended)
+        hipLaunchKernelGGL((k_finalize<T, INV_XPART>), dim3(nm), dim3(1024), 0, st, (const MemberDesc<T>*)md, nparts);
+    else
+        hipLaunchKernelGGL((k_finalize<T, INV_NPART>), dim3(nm), dim3(1024), 0, st, (const MemberDesc<T>*)md, nparts);
     return check_launch();
 }
 
@@ -211,6 +215,6 @@ int launch_finalize(const void* md, int nm, int nparts, hipStream_t st) {
     template int launch_c2c<T>(bool, int, const Grid3&, const void*, int, const void*, hipStream_t);          \
     template int launch_fused<T>(int, int, const Grid3&, const void*, int, const void*, int, hipStream_t);    \
     template int fused_partial_count<T>(int, const Grid3&);                                                   \
-    template int launch_finalize<T>(const void*, int, int, hipStream_t);
+    template int launch_finalize<T>(const void*, int, int, hipStream_t, bool);
 
 }  // namespace eifp

@@ -160,9 +160,9 @@ eifp_status eifp_init(eifp_solver** out, int nx, int ny, int nz, const eifp_doma
     INIT_TRY(alloc(&s->state, sb, &s->bytes));
     INIT_TRY(alloc(&s->scratch, sb, &s->bytes));
     INIT_TRY(alloc((void**)&s->partials, s->en.partial_bytes(), &s->bytes));
-    INIT_TRY(alloc((void**)&s->inv_dev, 8 * sizeof(double), &s->bytes));
+    INIT_TRY(alloc((void**)&s->inv_dev, INV_XPART * sizeof(double), &s->bytes));
     INIT_TRY(alloc(&s->desc_dev, sizeof s->desc_host, &s->bytes));
-    INIT_HIP(hipHostMalloc((void**)&s->inv_host, 8 * sizeof(double), hipHostMallocDefault));
+    INIT_HIP(hipHostMalloc((void**)&s->inv_host, INV_XPART * sizeof(double), hipHostMallocDefault));
     INIT_TRY(upload_desc(s, 0.0, 0.0));
     // upload: FP64 directly; FP32 through the scratch buffer (3 ns doubles = 6 ns floats)
     const size_t half = (size_t)3 * ns * sizeof(double);
@@ -281,6 +281,28 @@ eifp_status eifp_invariants(eifp_solver* s, eifp_invariant_set* out) {
     out->div_e_l2 = v[6];
     for (int i = 0; i < 7; ++i)
         if (!std::isfinite(v[i])) return fail(EIFP_ERR_NONFINITE, "invariant %d is not finite", i);
+    return EIFP_OK;
+}
+
+eifp_status eifp_invariants_ext(eifp_solver* s, eifp_invariant_ext_set* out) {
+    clear_error();
+    if (!s || !out) return fail(EIFP_ERR_INVALID_ARG, "NULL argument");
+    eifp_status st = s->en.passes(Z_FORWARD_EXT, fwd_desc(s), 1, s->stream, nullptr);
+    if (st != EIFP_OK) return st;
+    s->inv_current = true;  // the basic record is rewritten for the same state
+    EIFP_HIP_TRY(hipMemcpyAsync(s->inv_host, s->inv_dev, INV_XPART * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    EIFP_HIP_TRY(hipStreamSynchronize(s->stream));
+    const double* v = s->inv_host;
+    out->t = s->t;
+    out->steps_done = s->steps;
+    out->e2 = v[INV_E2];
+    for (int k = 0; k < 3; ++k) {
+        out->e3[k] = v[INV_E3X + k];
+        out->e4[k] = v[INV_E4X + k];
+    }
+    out->h2 = v[INV_H2];
+    for (int q = INV_NPART; q < INV_XPART; ++q)
+        if (!std::isfinite(v[q])) return fail(EIFP_ERR_NONFINITE, "extended invariant %d is not finite", q);
     return EIFP_OK;
 }
 

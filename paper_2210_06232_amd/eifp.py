@@ -95,6 +95,17 @@ class eifp_server_stat_set(ctypes.Structure):
                [("mean_batch", ctypes.c_double)]
 
 
+class eifp_invariant_ext_set(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_double),
+        ("steps_done", ctypes.c_longlong),
+        ("e2", ctypes.c_double),
+        ("e3", ctypes.c_double * 3),
+        ("e4", ctypes.c_double * 3),
+        ("h2", ctypes.c_double),
+    ]
+
+
 # every symbol the header declares, with (restype, argtypes)
 _VP = ctypes.c_void_p
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -107,6 +118,7 @@ SIGNATURES = {
     "eifp_jump": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_longlong]),
     "eifp_step_timed": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_longlong, _DP]),
     "eifp_invariants": (ctypes.c_int, [_VP, ctypes.POINTER(eifp_invariant_set)]),
+    "eifp_invariants_ext": (ctypes.c_int, [_VP, ctypes.POINTER(eifp_invariant_ext_set)]),
     "eifp_fields": (ctypes.c_int, [_VP, _DP, _DP]),
     "eifp_fields_device": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int]),
     "eifp_spectrum": (ctypes.c_int, [_VP, _DP]),
@@ -231,6 +243,12 @@ def eifp_invariants(handle) -> dict:
     return _inv_dict(inv)
 
 
+def eifp_invariants_ext(handle) -> dict:
+    x = eifp_invariant_ext_set()
+    _check(load().eifp_invariants_ext(handle, ctypes.byref(x)), "eifp_invariants_ext")
+    return {"t": x.t, "steps_done": x.steps_done, "E2": x.e2, "E3": list(x.e3), "E4": list(x.e4), "H2": x.h2}
+
+
 def eifp_fields(handle, shape):
     """shape = (nx, ny, nz); returns (H, E) as float64 [3, nz, ny, nx]."""
     nx, ny, nz = shape
@@ -301,6 +319,9 @@ class Solver:
 
     def invariants(self) -> dict:
         return eifp_invariants(self.handle)
+
+    def invariants_ext(self) -> dict:
+        return eifp_invariants_ext(self.handle)
 
     def fields(self):
         return eifp_fields(self.handle, self.shape)

@@ -1,0 +1,66 @@
+"""Extended invariants of Thms 4.1 and 4.3 (E2, E3_k, E4_k, H2) from the GPU's spectral
+sums against the oracle's physical-space evaluation, and their conservation."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2210_06232_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DOMAIN = (0.0, 2 * math.pi, -1.0, 4 * math.pi - 1.0, 0.5, 2.5)
+
+
+def eifp():
+    from paper_2210_06232_amd import eifp as m
+    m.load()
+    return m
+
+
+def compare(ext, ref, tol):
+    # H2 may be near zero: scale it by sqrt(E2 * sum E4) (Cauchy-Schwarz size of the form)
+    scale_h2 = math.sqrt(ref["E2"] * sum(ref[f"E4_{k}"] for k in "xyz"))
+    assert abs(ext["E2"] - ref["E2"]) <= tol * ref["E2"]
+    # a direction may carry no modes at all (E3_k = E4_k = 0): scale by the sum over k
+    e3 = sum(ref[f"E3_{k}"] for k in "xyz")
+    e4 = sum(ref[f"E4_{k}"] for k in "xyz")
+    for i, k in enumerate("xyz"):
+        assert abs(ext["E3"][i] - ref[f"E3_{k}"]) <= tol * max(ref[f"E3_{k}"], 1e-3 * e3), k
+        assert abs(ext["E4"][i] - ref[f"E4_{k}"]) <= tol * max(ref[f"E4_{k}"], 1e-3 * e4), k
+    assert abs(ext["H2"] - ref["H2"]) <= tol * scale_h2
+
+
+@pytest.mark.parametrize("shape,kind", [((24, 16, 32), "divfree"), ((16, 12, 8), "noise"), ((32, 48, 16), "divfree")])
+def test_extended_invariants_match_oracle_fp64(shape, kind):
+    m = eifp()
+    if kind == "divfree":
+        H, E = inputs.random_fields(shape, DOMAIN, workload=9, p=1.5)
+    else:
+        H, E = inputs.white_noise_fields(shape, seed=91)
+    mu, eps = 1.3, 0.7
+    with m.Solver(H, E, DOMAIN, mu, eps, "fp64") as s:
+        ext = s.invariants_ext()
+        basic = s.invariants()
+    ref = orc.invariants(H, E, DOMAIN, mu, eps)
+    compare(ext, ref, 1e-12)
+    assert abs(basic["energy"] - ref["E1"]) <= 1e-12 * ref["E1"]
+
+
+def test_extended_invariants_conserved_and_fp32():
+    m = eifp()
+    shape = (32, 32, 32)
+    H, E = inputs.random_fields(shape, DOMAIN, workload=10, p=1.5)
+    mu, eps = 1.0, 2.0
+    ref = orc.invariants(H, E, DOMAIN, mu, eps)
+    with m.Solver(H, E, DOMAIN, mu, eps, "fp64") as s:
+        e0 = s.invariants_ext()
+        s.step(0.07, 50)
+        e1 = s.invariants_ext()
+    compare(e1, ref, 1e-12)  # conserved: the state after 50 steps has the initial values
+    assert e1["steps_done"] == 50 and e0["steps_done"] == 0
+    with m.Solver(H, E, DOMAIN, mu, eps, "fp32") as s:
+        s.step(0.07, 5)
+        e32 = s.invariants_ext()
+    compare(e32, ref, 1e-5)
