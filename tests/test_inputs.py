@@ -41,3 +41,17 @@ def test_standing_wave_normalisation_and_divergence():
     H, E, dom = inputs.standing_wave(16, 0.0, 1.0, 2.0, t0=0.3)
     inv = orc.invariants(H, E, dom, 1.0, 2.0)
     assert inv["divH_linf"] < 1e-13 and inv["divE_linf"] < 1e-13
+
+
+def test_subsampling_evaluates_the_same_field():
+    # a field given on the fine grid, read at the coarse grid's points, is the same
+    # trigonometric polynomial evaluated there
+    from paper_2210_06232_amd import convergence
+    n, m = 24, 8
+    x = np.arange(n) * 2 * np.pi / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    F = np.stack([np.cos(2 * X + Y), np.sin(X - 3 * Z), np.cos(Y) * np.sin(Z)])
+    xc = np.arange(m) * 2 * np.pi / m
+    Zc, Yc, Xc = np.meshgrid(xc, xc, xc, indexing="ij")
+    Fc = np.stack([np.cos(2 * Xc + Yc), np.sin(Xc - 3 * Zc), np.cos(Yc) * np.sin(Zc)])
+    assert np.allclose(convergence.subsample(F, m), Fc, atol=1e-14)
