@@ -23,12 +23,19 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 
 template <typename T>
 eifp_status upload_table(void** dst, int n, long long* bytes) {
-    // exp(-2 pi i k / n), k < n, formed in FP64 and rounded to T
-    std::vector<T> h(2 * (size_t)n);
+    // exp(-2 pi i k / n), k < n, formed in FP64 and rounded to T; an FP32 table carries
+    // the rounding remainders (FP64 value - rounded value, rounded) as entries n..2n-1
+    const int parts = TwParts<T>::value;
+    std::vector<T> h(2 * (size_t)n * parts);
     for (int k = 0; k < n; ++k) {
         const double a = kTwoPi * (double)k / (double)n;
-        h[2 * k] = (T)std::cos(a);
-        h[2 * k + 1] = (T)-std::sin(a);
+        const double c = std::cos(a), s = -std::sin(a);
+        h[2 * k] = (T)c;
+        h[2 * k + 1] = (T)s;
+        if (parts == 2) {
+            h[2 * (n + k)] = (T)(c - (double)h[2 * k]);
+            h[2 * (n + k) + 1] = (T)(s - (double)h[2 * k + 1]);
+        }
     }
     if (hipMalloc(dst, h.size() * sizeof(T)) != hipSuccess) {
         *dst = nullptr;

@@ -30,6 +30,56 @@ template <typename T> __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b
     return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 template <typename T> __device__ __forceinline__ cpx<T> conj(cpx<T> a) { return {a.x, -a.y}; }
+
+// Twiddle tables hold exp(-2 pi i k / n), k < n, formed in FP64.  In FP32 the rounded
+// values are biased in modulus (sqrt(2)/2, for one, rounds down and enters every
+// stage), so every transform would lose about one unit roundoff of energy and the
+// error of a long FP32 run would grow linearly.  FP32 tables therefore carry a second
+// part, lo = (FP64 value - hi) rounded, at index k + n, and every FP32 twiddle product
+// adds the lo terms inside its FMA chain, before the single final rounding.
+template <typename T> struct TwParts { static constexpr int value = 1; };
+template <> struct TwParts<float> { static constexpr int value = 2; };
+
+// v * w or v * conj(w) for the table entry k of a table of n entries (lo part at k + n;
+// CT = false uses the rounded value alone)
+template <bool CONJ, bool CT = true, typename T>
+__device__ __forceinline__ cpx<T> twmul(const cpx<T>* tw, int k, int n, cpx<T> v) {
+    const cpx<T> h = tw[k];
+    if constexpr (TwParts<T>::value == 1 || !CT) {
+        return CONJ ? cmulc(v, h) : cmul(v, h);
+    } else {
+        const cpx<T> l = tw[k + n];
+        if (CONJ)
+            return {__builtin_fmaf(v.x, h.x, __builtin_fmaf(v.y, h.y, __builtin_fmaf(v.x, l.x, v.y * l.y))),
+                    __builtin_fmaf(v.y, h.x, __builtin_fmaf(-v.x, h.y, __builtin_fmaf(v.y, l.x, -(v.x * l.y))))};
+        return {__builtin_fmaf(v.x, h.x, __builtin_fmaf(-v.y, h.y, __builtin_fmaf(v.x, l.x, -(v.y * l.y)))),
+                __builtin_fmaf(v.x, h.y, __builtin_fmaf(v.y, h.x, __builtin_fmaf(v.x, l.y, v.y * l.x)))};
+    }
+}
+
+// v * (c + i s) for FP64 constants c, s: in FP32 with the same two-part compensation
+template <typename T>
+__device__ __forceinline__ cpx<T> rotc(double c, double s, cpx<T> v) {
+    if constexpr (sizeof(T) == 8) {
+        return {v.x * c - v.y * s, v.x * s + v.y * c};
+    } else {
+        const float ch = (float)c, sh = (float)s;
+        const float cl = (float)(c - (double)ch), sl = (float)(s - (double)sh);
+        return {__builtin_fmaf(v.x, ch, __builtin_fmaf(-v.y, sh, __builtin_fmaf(v.x, cl, -(v.y * sl)))),
+                __builtin_fmaf(v.x, sh, __builtin_fmaf(v.y, ch, __builtin_fmaf(v.x, sl, v.y * cl)))};
+    }
+}
+
+// a * c for an FP64 constant c, compensated in FP32
+template <typename T>
+__device__ __forceinline__ T mulc(double c, T a) {
+    if constexpr (sizeof(T) == 8) {
+        return a * c;
+    } else {
+        const float ch = (float)c, cl = (float)(c - (double)ch);
+        return __builtin_fmaf(a, ch, a * cl);
+    }
+}
 template <typename T> __device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) { return {a.x * s, a.y * s}; }
 // multiply by i and by -i
 template <typename T> __device__ __forceinline__ cpx<T> muli(cpx<T> a) { return {-a.y, a.x}; }
@@ -61,9 +111,7 @@ __device__ __forceinline__ cpx<T> twc(int e, cpx<T> v) {
         return plus_i ? muli(v) : mulmi(v);
     }
     const int j = (48 / R) * e;
-    const T c = (T)cos48(j);
-    const T s = INV ? (T)sin48(j) : (T)-sin48(j);
-    return {v.x * c - v.y * s, v.x * s + v.y * c};
+    return rotc<T>(cos48(j), INV ? sin48(j) : -sin48(j), v);
 }
 
 // ---------------------------------------------------------------------------------
@@ -86,12 +134,13 @@ template <bool INV, typename T> struct Dft<2, INV, T> {
 template <bool INV, typename T> struct Dft<3, INV, T> {
     __device__ __forceinline__ static void run(cpx<T>* a) {
         // w = exp(-+2 pi i/3) = -1/2 -+ i sqrt(3)/2
-        const T h = (T)0.8660254037844386;
+        constexpr double h = 0.8660254037844386;
         const cpx<T> s = a[1] + a[2];
         const cpx<T> d = a[1] - a[2];
         const cpx<T> m = {a[0].x - (T)0.5 * s.x, a[0].y - (T)0.5 * s.y};
         // i * sin * d with sin = -+sqrt(3)/2
-        const cpx<T> r = INV ? cpx<T>{-h * d.y, h * d.x} : cpx<T>{h * d.y, -h * d.x};
+        const T hy = mulc<T>(h, d.y), hx = mulc<T>(h, d.x);
+        const cpx<T> r = INV ? cpx<T>{-hy, hx} : cpx<T>{hy, -hx};
         a[0] = a[0] + s;
         a[1] = m + r;
         a[2] = m - r;
@@ -221,7 +270,7 @@ __host__ __device__ constexpr int m_last(int idx) {
 // Runs stages s..S-1.  v holds stage-s inputs: v[u R + r] = x[j + r N/R], j = t + T u.
 // tw[k * TWS] = exp(-2 pi i k / N) for k < N (forward table; conj for the inverse).
 // Lds provides st(pos, v), ld(pos) for this thread's pencil and sync().
-template <class P, int s, bool INV, int TWS, typename T, class Lds>
+template <class P, int s, bool INV, int TWS, bool CT = true, typename T, class Lds>
 __device__ __forceinline__ void fft_stages(cpx<T> (&v)[P::E], int t, Lds& lds, const cpx<T>* __restrict__ tw) {
     constexpr int N = P::N, E = P::E, TT = P::T;
     constexpr int R = P::R[s];
@@ -234,8 +283,7 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[P::E], int t, Lds& lds, c
             const int jm = j % NS;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                const cpx<T> w = tw[(jm * r * (N / (NS * R))) * TWS];
-                v[u * R + r] = INV ? cmulc(v[u * R + r], w) : cmul(v[u * R + r], w);
+                v[u * R + r] = twmul<INV, CT>(tw, (jm * r * (N / (NS * R))) * TWS, N * TWS, v[u * R + r]);
             }
         }
         Dft<R, INV, T>::run(&v[u * R]);
@@ -257,7 +305,7 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[P::E], int t, Lds& lds, c
             for (int r = 0; r < R2; ++r) v[u * R2 + r] = lds.ld(j + r * (N / R2));
         }
         lds.after_load();
-        fft_stages<P, s + 1, INV, TWS>(v, t, lds, tw);
+        fft_stages<P, s + 1, INV, TWS, CT>(v, t, lds, tw);
     }
 }
 
@@ -281,9 +329,9 @@ __device__ __forceinline__ void last_to_first(cpx<T> (&v)[P::E]) {
     for (int i = 0; i < P::E; ++i) v[i] = w[i];
 }
 
-template <class P, bool INV, int TWS, typename T, class Lds>
+template <class P, bool INV, int TWS, bool CT = true, typename T, class Lds>
 __device__ __forceinline__ void fft_pencil(cpx<T> (&v)[P::E], int t, Lds& lds, const cpx<T>* __restrict__ tw) {
-    fft_stages<P, 0, INV, TWS>(v, t, lds, tw);
+    fft_stages<P, 0, INV, TWS, CT>(v, t, lds, tw);
 }
 
 // LDS views.  Columns: a tile of B pencils stored [pos][col] (real and imaginary parts
@@ -352,7 +400,8 @@ struct LdsRows {
 // between this copy and the first read.
 template <typename T>
 __device__ __forceinline__ void stage_table(cpx<T>* dst, const cpx<T>* __restrict__ src, int n) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+    // n entries, plus their lo parts for FP32 tables
+    for (int i = threadIdx.x; i < n * TwParts<T>::value; i += blockDim.x) dst[i] = src[i];
 }
 
 // Raw buffer access (gfx9 descriptor): one SGPR descriptor per array, a per-lane VGPR

@@ -74,7 +74,7 @@ k_x_fwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
     constexpr int M = P::N, E = P::E, TT = P::T, LD = M + 1;
     __shared__ T s_re[NP * LD];
     __shared__ T s_im[NP * LD];
-    __shared__ cpx<T> s_tw[2 * M];
+    __shared__ cpx<T> s_tw[2 * M * TwParts<T>::value];
     stage_table(s_tw, twx, 2 * M);
     const cpx<T>* src = md[blockIdx.y].state;
     cpx<T>* dst = md[blockIdx.y].work;
@@ -105,7 +105,7 @@ k_x_fwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
             const cpx<T> zc = conj(lds.ld(M - k));
             const cpx<T> ev = scale(z + zc, (T)0.5);
             const cpx<T> od = scale(mulmi(z - zc), (T)0.5);  // (Z - conj Z')/(2i)
-            r = ev + cmul(s_tw[k], od);
+            r = ev + twmul<false>(s_tw, k, 2 * M, od);
         }
         if (active) out[k] = r;
     }
@@ -118,7 +118,7 @@ k_x_inv(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
     constexpr int M = P::N, E = P::E, TT = P::T, LD = M + 1;
     __shared__ T s_re[NP * LD];
     __shared__ T s_im[NP * LD];
-    __shared__ cpx<T> s_tw[2 * M];
+    __shared__ cpx<T> s_tw[2 * M * TwParts<T>::value];
     stage_table(s_tw, twx, 2 * M);
     const cpx<T>* src = md[blockIdx.y].work;
     cpx<T>* dst = md[blockIdx.y].state;
@@ -142,7 +142,7 @@ k_x_inv(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
             v[i] = {x.x + x.y, x.x - x.y};
         } else {
             const cpx<T> xc = conj(lds.ld(M - k));
-            v[i] = (x + xc) + muli(cmulc(x - xc, s_tw[k]));
+            v[i] = (x + xc) + muli(twmul<true>(s_tw, k, 2 * M, x - xc));
         }
     }
     __syncthreads();
@@ -215,7 +215,7 @@ k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, l
     constexpr int NP = P::N, E = P::E, TT = P::T;
     __shared__ T s_re[NP * col_pitch(B)];
     __shared__ T s_im[NP * col_pitch(B)];
-    __shared__ cpx<T> s_tw[NP];
+    __shared__ cpx<T> s_tw[NP * TwParts<T>::value];
     stage_table(s_tw, tw, NP);
     const int c = threadIdx.x % B, t = threadIdx.x / B;
     int tx, ty;
@@ -334,6 +334,9 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[Q], double* __r
 // which is the c/s matrix of Prop. 2.2 applied as in Alg. 2 step 4 (c = k k^T +
 // cos(theta) (I - k k^T), s_12 = i sin(theta) k_z, ...).  |b| = 0 keeps the mode.
 // All coefficients are formed in FP64 and rounded to T; everything is scaled by 1/N_S.
+#ifndef EIFP_PROP_COMP
+#define EIFP_PROP_COMP 1
+#endif
 template <typename T>
 __device__ __forceinline__ void propagate_mode(cpx<T>* h, cpx<T>* e, double bx, double by, double bz, const PropParams& pp) {
     // |b| = 0 needs no branch: theta = 0 gives cos = 1, sin = 0 and the k terms drop out
@@ -343,6 +346,57 @@ __device__ __forceinline__ void propagate_mode(cpx<T>* h, cpx<T>* e, double bx, 
     // the phase in half-turns, theta / pi, so that the reduction is exact for any tau
     double sn, cs;
     sincospi(pp.tau_s_over_pi * bn, &sn, &cs);
+    if constexpr (sizeof(T) == 4 && EIFP_PROP_COMP) {
+        // FP32: every coefficient of the transverse rotation (cos, sin, the unit wave
+        // vector in the cross products) enters as a rounded part plus its remainder,
+        // folded into the FMA chain before the final rounding, so the per-mode rotation
+        // is not biased in modulus from step to step
+        const double kd[3] = {bx * ib, by * ib, bz * ib};
+        float kh_[3], kl_[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            kh_[c] = (float)kd[c];
+            kl_[c] = (float)(kd[c] - (double)kh_[c]);
+        }
+        const double cTd = cs * pp.inv_ns, sEd = sn * pp.re * pp.inv_ns, sHd = sn * pp.rh * pp.inv_ns;
+        const float cTh = (float)cTd, cTl = (float)(cTd - (double)cTh);
+        const float sEh = (float)sEd, sEl = (float)(sEd - (double)sEh);
+        const float sHh = (float)sHd, sHl = (float)(sHd - (double)sHh);
+        const float dL = (float)((1.0 - cs) * pp.inv_ns);
+        const cpx<float> kh = {kh_[0] * (float)h[0].x + kh_[1] * (float)h[1].x + kh_[2] * (float)h[2].x,
+                               kh_[0] * (float)h[0].y + kh_[1] * (float)h[1].y + kh_[2] * (float)h[2].y};
+        const cpx<float> ke = {kh_[0] * (float)e[0].x + kh_[1] * (float)e[1].x + kh_[2] * (float)e[2].x,
+                               kh_[0] * (float)e[0].y + kh_[1] * (float)e[1].y + kh_[2] * (float)e[2].y};
+        // (k x U)_c = k_a U_b - k_b U_a with (a, b) = (y, z), (z, x), (x, y)
+        auto cross = [&](const float* ur, int c) {
+            const int a = (c + 1) % 3, b = (c + 2) % 3;
+            return __builtin_fmaf(kh_[a], ur[b],
+                                  __builtin_fmaf(-kh_[b], ur[a], __builtin_fmaf(kl_[a], ur[b], -(kl_[b] * ur[a]))));
+        };
+        const float her[3] = {(float)h[0].x, (float)h[1].x, (float)h[2].x}, hei[3] = {(float)h[0].y, (float)h[1].y, (float)h[2].y};
+        const float eer[3] = {(float)e[0].x, (float)e[1].x, (float)e[2].x}, eei[3] = {(float)e[0].y, (float)e[1].y, (float)e[2].y};
+        float xer[3], xei[3], xhr[3], xhi[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xer[c] = cross(eer, c);
+            xei[c] = cross(eei, c);
+            xhr[c] = cross(her, c);
+            xhi[c] = cross(hei, c);
+        }
+        // H' = cT H + dL k (k.H) - sE i (k x E);  E' = cT E + dL k (k.E) + sH i (k x H);  i (a + ib) = -b + ia
+        auto comb = [&](float u, float x, float lon, float sh, float sl) {
+            return __builtin_fmaf(cTh, u, __builtin_fmaf(sh, x, __builtin_fmaf(cTl, u, __builtin_fmaf(sl, x, lon))));
+        };
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float dk = dL * kh_[c];
+            const cpx<float> hn = {comb(her[c], xei[c], dk * kh.x, sEh, sEl), comb(hei[c], -xer[c], dk * kh.y, sEh, sEl)};
+            const cpx<float> en = {comb(eer[c], -xhi[c], dk * ke.x, sHh, sHl), comb(eei[c], xhr[c], dk * ke.y, sHh, sHl)};
+            h[c] = {(T)hn.x, (T)hn.y};
+            e[c] = {(T)en.x, (T)en.y};
+        }
+        return;
+    }
     const T kx = (T)(bx * ib), ky = (T)(by * ib), kz = (T)(bz * ib);
     const T cT = (T)(cs * pp.inv_ns);                 // transverse part
     const T dL = (T)((1.0 - cs) * pp.inv_ns);         // longitudinal minus transverse
@@ -380,6 +434,15 @@ template <typename T, int N> struct ZWaves {
     static constexpr int value = (N % 3 == 0) ? 1 : (sizeof(T) == 8 ? EIFP_ZWAVES64 : EIFP_ZWAVES32);
 };
 
+// FP32 stage twiddles of the fused pass with (1) or without (0) the compensation terms.
+// With them an FP32 run's error grows like the square root of the step count instead
+// of linearly, but the extra live registers spill and the pass takes ~60% longer; the
+// default leaves the fused pass's table products uncompensated (its bias alone is a
+// quarter of the uncompensated transform's) and compensates everything else.
+#ifndef EIFP_FUSED_CT
+#define EIFP_FUSED_CT 0
+#endif
+
 // scheduling fences of the fused pass: bit 0 between components' transforms, bit 1
 // between modes of the propagator
 #ifndef EIFP_FUSED_SB
@@ -397,7 +460,7 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
         const cpx<T>* __restrict__ tw, int want_inv) {
     constexpr int NZ = P::N, E = P::E, TT = P::T, NT = P::T * B;
     __shared__ T s_x[2 * 2 * NZ * zcol_pitch(B)];
-    __shared__ cpx<T> s_tw[NZ];
+    __shared__ cpx<T> s_tw[NZ * TwParts<T>::value];
     constexpr int Q = NQ<MODE>::value;
     __shared__ double s_red[((NT + 63) / 64) * Q];
     stage_table(s_tw, tw, NZ);
@@ -427,7 +490,7 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
             int tq = t, cq = c;
             asm volatile("" : "+v"(tq), "+v"(cq));
             lds.c = cq;
-            fft_pencil<P, false, 1>(v[q], tq, lds, s_tw);
+            fft_pencil<P, false, 1, EIFP_FUSED_CT != 0>(v[q], tq, lds, s_tw);
             if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);  // one component's temporaries live at a time
         }
     }
@@ -478,7 +541,7 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
             int tq = t, cq = c;
             asm volatile("" : "+v"(tq), "+v"(cq));
             lds.c = cq;
-            fft_pencil<P, true, 1>(v[q], tq, lds, s_tw);
+            fft_pencil<P, true, 1, EIFP_FUSED_CT != 0>(v[q], tq, lds, s_tw);
             store_col<T, P>(v[q], make_rsrc(buf + q * cs, cbytes), voff, sstep, active);
             if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
         }
