@@ -341,8 +341,8 @@ template <typename T>
 __device__ __forceinline__ void propagate_mode(cpx<T>* h, cpx<T>* e, double bx, double by, double bz, const PropParams& pp) {
     // |b| = 0 needs no branch: theta = 0 gives cos = 1, sin = 0 and the k terms drop out
     const double b2 = bx * bx + by * by + bz * bz;
-    const double bn = sqrt(b2);
-    const double ib = b2 > 0.0 ? 1.0 / bn : 0.0;
+    const double ib = b2 > 0.0 ? rsqrt(b2) : 0.0;  // 1/|b| (0 for the zero mode)
+    const double bn = b2 * ib;                      // |b|
     // the phase in half-turns, theta / pi, so that the reduction is exact for any tau
     double sn, cs;
     sincospi(pp.tau_s_over_pi * bn, &sn, &cs);

@@ -25,6 +25,7 @@ SHAPES = [
     (512, 4, 4), (4, 512, 4), (4, 4, 512),
 ]
 DOMAIN = (0.0, 2 * math.pi, -1.0, 4 * math.pi - 1.0, 0.5, 2.5)
+CUBE_2PI = (0.0, 2 * math.pi, 0.0, 2 * math.pi, 0.0, 2 * math.pi)
 
 
 def eifp():
@@ -195,6 +196,36 @@ def test_full_size_256_exact_plane_waves(prec, tol):
     scale = np.max(np.abs(Hx))
     for c in range(3):
         assert np.max(np.abs(Hg[c][idx] - Hx[c][idx])) <= 10 * tol * scale
+
+
+def test_full_size_512_fp32_exact_plane_waves():
+    # the large single solve: 512^3 on [0,2pi]^3, FP32 fields, mu = 1, eps = 1.5,
+    # tau = 0.02, in the launch configuration the solver uses at that size; plane waves
+    # are evolved exactly, so the closed form is the reference everywhere.  Stepping and
+    # a jump over the same span are both checked.
+    m = eifp()
+    shape = (512, 512, 512)
+    dom = CUBE_2PI
+    mu, eps, tau, n = 1.0, 1.5, 0.02, 5
+    modes = _modes(dom, np.random.default_rng(512), 3, 170)
+    H0, E0 = _plane_wave_sum(shape, dom, 0.0, mu, eps, modes)
+    Hx, Ex = _plane_wave_sum(shape, dom, tau * n, mu, eps, modes)
+    rng = np.random.default_rng(5)
+    idx = tuple(rng.integers(0, 512, size=(3, 4096)))
+    scale = max(np.max(np.abs(Hx)), np.max(np.abs(Ex)))
+    with m.Solver(H0, E0, dom, mu, eps, "fp32") as s:
+        del H0, E0
+        s.step(tau, n)
+        Hg, Eg = s.fields()
+        assert energy_rel_error(Hg, Eg, Hx, Ex, mu, eps) <= 2e-5
+        for c in range(3):
+            assert np.max(np.abs(Hg[c][idx] - Hx[c][idx])) <= 1e-5 * scale
+            assert np.max(np.abs(Eg[c][idx] - Ex[c][idx])) <= 1e-5 * scale
+        del Hg, Eg
+        s.jump(tau, n)  # anchored at step n: reaches 2 n tau
+        Hg, Eg = s.fields()
+    Hx, Ex = _plane_wave_sum(shape, dom, 2 * tau * n, mu, eps, modes)
+    assert energy_rel_error(Hg, Eg, Hx, Ex, mu, eps) <= 2e-5
 
 
 def test_full_size_128_one_step_vs_oracle():
