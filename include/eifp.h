@@ -119,9 +119,10 @@ eifp_status eifp_jump(eifp_solver *s, double tau, long long nsteps);
 /* Same as eifp_step, and also measures each pass with HIP events recorded on the
  * solver's stream around every kernel.  pass_ms[0..5] receive the summed durations in
  * milliseconds of: x-forward (real-to-complex), z-forward, fused y (forward,
- * propagator, invariant partials, inverse), z-inverse, x-inverse (complex-to-real),
- * invariant finalize.  Synchronises the
- * stream before returning.  Errors as eifp_step, plus INVALID_ARG for NULL pass_ms. */
+ * propagator, invariant partials, inverse), z-inverse (which also finalizes the
+ * invariants, in one extra workgroup), x-inverse (complex-to-real), and the gap where a
+ * separate finalize would run (kept for layout; near zero).  Synchronises the stream
+ * before returning.  Errors as eifp_step, plus INVALID_ARG for NULL pass_ms. */
 eifp_status eifp_step_timed(eifp_solver *s, double tau, long long nsteps, double *pass_ms);
 
 /* Invariants of the current state (Sec. 4).  Synchronises the solver's stream.  If no
@@ -292,6 +293,7 @@ eifp_status eifp_server_stats(eifp_server *sv, eifp_server_stat_set *out);
 eifp_status eifp_server_drain(eifp_server *sv, int timeout_ms);
 
 /* Stop the loop, drop queued requests, wait for running chunks, free everything.
+ * No other call on this server may be in progress when it is made, or follow it.
  * NULL is accepted. */
 eifp_status eifp_server_destroy(eifp_server *sv);
 

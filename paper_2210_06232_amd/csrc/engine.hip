@@ -66,7 +66,9 @@ eifp_status run_passes(const Engine& en, int mode, const void* md, int nm, hipSt
         return rc_to_status(rc, "fused y pass");
     if (ev) EIFP_HIP_TRY(hipEventRecord(ev[3], st));
     if (mode == Z_STEP) {
-        if ((rc = launch_c2c<T>(true, AXIS_Z, en.g, md, nm, en.twz, st))) return rc_to_status(rc, "z inverse");
+        // the z inverse also finalizes the invariant partials (one extra workgroup per member)
+        if ((rc = launch_c2c<T>(true, AXIS_Z, en.g, md, nm, en.twz, st, want_inv ? en.nparts : 0)))
+            return rc_to_status(rc, "z inverse");
         if (ev) EIFP_HIP_TRY(hipEventRecord(ev[4], st));
         if ((rc = launch_x<T>(true, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x inverse");
         if (ev) EIFP_HIP_TRY(hipEventRecord(ev[5], st));
@@ -74,7 +76,7 @@ eifp_status run_passes(const Engine& en, int mode, const void* md, int nm, hipSt
         EIFP_HIP_TRY(hipEventRecord(ev[4], st));
         EIFP_HIP_TRY(hipEventRecord(ev[5], st));
     }
-    if (want_inv && (rc = launch_finalize<T>(md, nm, en.nparts, st, mode == Z_FORWARD_EXT)))
+    if (mode != Z_STEP && want_inv && (rc = launch_finalize<T>(md, nm, en.nparts, st, mode == Z_FORWARD_EXT)))
         return rc_to_status(rc, "finalize");
     if (ev) EIFP_HIP_TRY(hipEventRecord(ev[6], st));
     return EIFP_OK;
@@ -94,9 +96,9 @@ eifp_status run_jump(const Engine& en, const void* md, int nm, hipStream_t st, b
     int rc;
     if ((rc = launch_fused<T>(Z_JUMP, AXIS_Y, en.g, md, nm, en.twy, want_inv ? 1 : 0, st)))
         return rc_to_status(rc, "fused jump pass");
-    if ((rc = launch_c2c<T>(true, AXIS_Z, en.g, md, nm, en.twz, st))) return rc_to_status(rc, "z inverse");
+    if ((rc = launch_c2c<T>(true, AXIS_Z, en.g, md, nm, en.twz, st, want_inv ? en.nparts : 0)))
+        return rc_to_status(rc, "z inverse");
     if ((rc = launch_x<T>(true, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x inverse");
-    if (want_inv && (rc = launch_finalize<T>(md, nm, en.nparts, st))) return rc_to_status(rc, "finalize");
     return EIFP_OK;
 }
 

@@ -177,29 +177,113 @@ __device__ __forceinline__ void store_col(const cpx<T> (&v)[P::E], __amdgpu_buff
 }
 
 // ---------------------------------------------------------------------------------
+// deterministic compensated finalize of the invariant partials
+// ---------------------------------------------------------------------------------
+// Grid: one block per member.  out (member's inv): [0] E1 [1] H1 [2..4] M1
+// [5] ||div~(mu H)||_N [6] ||div~(eps E)||_N; extended record: [8] E2 [9..11] E3
+// [12..14] E4 [15] H2
+__device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
+    const double t = s + x;
+    c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+}
+
+// Thread j sums records j, j + 1024, ... (each record: Q contiguous doubles) with
+// Neumaier compensation, then the 1024 (sum, compensation) pairs are combined by a
+// fixed xor-butterfly inside each wave and a fixed loop over the 16 waves: the same
+// partials always give the same bits.
+// One member: thread j of the NT-thread workgroup sums records j, j + NT, ... (each
+// record: Q contiguous doubles) with Neumaier compensation, then the (sum,
+// compensation) pairs are combined by a fixed xor-butterfly inside each wave and a
+// fixed loop over the waves: the same partials always give the same bits.  s_w holds
+// 2 Q doubles per wave.
+template <int Q, int NT>
+__device__ __forceinline__ void finalize_member(const double* __restrict__ partials, int nparts, double* __restrict__ out,
+                                                double* s_w) {
+    static_assert(NT % 64 == 0, "whole waves");
+    constexpr int NW = NT / 64;
+    double s[Q], c[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s[q] = c[q] = 0.0;
+#pragma unroll 2
+    for (int j = threadIdx.x; j < nparts; j += NT) {
+        const double* rec = partials + (long)j * Q;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) neumaier_add(s[q], c[q], rec[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double os = __shfl_xor(s[q], off, 64), oc = __shfl_xor(c[q], off, 64);
+            c[q] += oc;
+            neumaier_add(s[q], c[q], os);
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            s_w[wid * 2 * Q + q] = s[q];
+            s_w[wid * 2 * Q + Q + q] = c[q];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double res[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            double a = 0.0, ca = 0.0;
+            for (int w = 0; w < NW; ++w) {
+                ca += s_w[w * 2 * Q + Q + q];
+                neumaier_add(a, ca, s_w[w * 2 * Q + q]);
+            }
+            res[q] = a + ca;
+        }
+        out[0] = res[INV_E1];
+        out[1] = res[INV_H1];
+        out[2] = res[INV_M1X];
+        out[3] = res[INV_M1Y];
+        out[4] = res[INV_M1Z];
+        out[5] = sqrt(res[INV_DIVH]);
+        out[6] = sqrt(res[INV_DIVE]);
+        out[7] = 0.0;
+#pragma unroll
+        for (int q = INV_NPART; q < Q; ++q) out[q] = res[q];
+    }
+}
+
+// Grid: one 1024-thread workgroup per member.
+template <typename T, int Q>
+__global__ void __launch_bounds__(1024) k_finalize(const MemberDesc<T>* __restrict__ md, int nparts) {
+    __shared__ double s_w[16 * 2 * Q];
+    finalize_member<Q, 1024>(md[blockIdx.x].partials, nparts, md[blockIdx.x].inv, s_w);
+}
+
+// ---------------------------------------------------------------------------------
 // tile numbering
 // ---------------------------------------------------------------------------------
 // The dispatcher deals workgroups to the 8 XCDs round robin by linear id, and each XCD
 // has its own L2.  With `on`, (blockIdx.x, blockIdx.y) are renumbered so that the
 // workgroups one XCD receives (linear ids congruent mod 8) cover a contiguous range of
 // tiles: neighbouring tiles, which share cache lines and DRAM pages, then run on the
-// same XCD at about the same time.  A bijection whenever gridDim.x * gridDim.y is a
-// multiple of 8 (otherwise the ids are left as they are).
+// same XCD at about the same time.  nxt: tile columns (blockIdx.x < nxt).  A bijection
+// whenever nxt * gridDim.y is a multiple of 8 (otherwise the ids are left as they are).
 #ifndef EIFP_FUSED_XCD
 #define EIFP_FUSED_XCD 1
 #endif
 #ifndef EIFP_C2C_XCD
 #define EIFP_C2C_XCD 0
 #endif
-__device__ __forceinline__ void xcd_tiles(bool on, int& tx, int& ty) {
+__device__ __forceinline__ void xcd_tiles(bool on, unsigned nxt, int& tx, int& ty) {
     tx = (int)blockIdx.x;
     ty = (int)blockIdx.y;
-    const unsigned n = gridDim.x * gridDim.y;
+    const unsigned n = nxt * gridDim.y;
     if (!on || (n & 7u) != 0) return;
-    const unsigned L = blockIdx.x + gridDim.x * blockIdx.y;
+    const unsigned L = blockIdx.x + nxt * blockIdx.y;
     const unsigned Lp = (L & 7u) * (n >> 3) + (L >> 3);
-    tx = (int)(Lp % gridDim.x);
-    ty = (int)(Lp / gridDim.x);
+    tx = (int)(Lp % nxt);
+    ty = (int)(Lp / nxt);
 }
 
 // ---------------------------------------------------------------------------------
@@ -207,19 +291,31 @@ __device__ __forceinline__ void xcd_tiles(bool on, int& tx, int& ty) {
 // ---------------------------------------------------------------------------------
 // Pencil positions are pstride apart; the third (outer) axis index blockIdx.y is ostride
 // apart; cs is the component stride; all in complex elements.  Grid: (x tiles, outer,
-// 6 x members); runs in place on work.
+// 6 x members); runs in place on work.  With fin_nparts > 0 the grid has one more tile
+// column, whose workgroup at outer index 0 and component 0 finalizes its member's
+// invariant partials (fin_nparts records) while the other workgroups transform: the
+// partials were written by the preceding fused pass, and the next one runs after this.
 template <typename T, class P, int B, bool INV>
 __global__ void __launch_bounds__(P::T * B)
 k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, long cs,
-      const cpx<T>* __restrict__ tw) {
+      const cpx<T>* __restrict__ tw, int fin_nparts) {
     constexpr int NP = P::N, E = P::E, TT = P::T;
+    __shared__ double s_w[((TT * B + 63) / 64) * 2 * INV_NPART];
+    const unsigned nxt = gridDim.x - (fin_nparts > 0 ? 1u : 0u);
+    if (blockIdx.x >= nxt) {  // the finalize column (uniform per workgroup)
+        if (blockIdx.y == 0 && blockIdx.z % 6 == 0) {
+            const MemberDesc<T>& m = md[blockIdx.z / 6];
+            finalize_member<INV_NPART, TT * B>(m.partials, fin_nparts, m.inv, s_w);
+        }
+        return;
+    }
     __shared__ T s_re[NP * col_pitch(B)];
     __shared__ T s_im[NP * col_pitch(B)];
     __shared__ cpx<T> s_tw[NP * TwParts<T>::value];
     stage_table(s_tw, tw, NP);
     const int c = threadIdx.x % B, t = threadIdx.x / B;
     int tx, ty;
-    xcd_tiles(EIFP_C2C_XCD, tx, ty);
+    xcd_tiles(EIFP_C2C_XCD, nxt, tx, ty);
     const int col = tx * B + c;
     const int o = ty;
     const int member = blockIdx.z / 6, comp = blockIdx.z % 6;
@@ -422,6 +518,56 @@ __device__ __forceinline__ void propagate_mode(cpx<T>* h, cpx<T>* e, double bx, 
     }
 }
 
+// Per-thread sums of the basic invariants along one y pencil.  The thread's column (so
+// b_x and the packed-column weight) and its z index (b_z) are fixed, so only the terms
+// that vary along the pencil are summed per mode; b_x, b_z, the weight and the
+// material factors are applied once, in finish().
+struct PencilSums {
+    double h2 = 0, e2 = 0;               // |H|^2, |E|^2
+    double chx = 0, chy = 0, chz = 0;    // (Re H x Im H)_x, b_y (..)_y, (..)_z
+    double cex = 0, cey = 0, cez = 0;    // the same for E
+    double q = 0, qy = 0;                // Im H . Re E - Re H . Im E, and b_y times it
+    double dh = 0, de = 0;               // |b . H|^2, |b . E|^2
+    template <typename T>
+    __device__ __forceinline__ void add(double bx, double by, double bz, const cpx<T>* h, const cpx<T>* e) {
+        const double hr[3] = {dreal(h[0].x), dreal(h[1].x), dreal(h[2].x)};
+        const double hi[3] = {dreal(h[0].y), dreal(h[1].y), dreal(h[2].y)};
+        const double er[3] = {dreal(e[0].x), dreal(e[1].x), dreal(e[2].x)};
+        const double ei[3] = {dreal(e[0].y), dreal(e[1].y), dreal(e[2].y)};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            h2 += hr[c] * hr[c] + hi[c] * hi[c];
+            e2 += er[c] * er[c] + ei[c] * ei[c];
+        }
+        chx += hr[1] * hi[2] - hr[2] * hi[1];
+        chy += by * (hr[2] * hi[0] - hr[0] * hi[2]);
+        chz += hr[0] * hi[1] - hr[1] * hi[0];
+        cex += er[1] * ei[2] - er[2] * ei[1];
+        cey += by * (er[2] * ei[0] - er[0] * ei[2]);
+        cez += er[0] * ei[1] - er[1] * ei[0];
+        double qq = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) qq += hi[c] * er[c] - hr[c] * ei[c];
+        q += qq;
+        qy += by * qq;
+        const double dhr = bx * hr[0] + by * hr[1] + bz * hr[2], dhi = bx * hi[0] + by * hi[1] + bz * hi[2];
+        const double der = bx * er[0] + by * er[1] + bz * er[2], dei = bx * ei[0] + by * ei[1] + bz * ei[2];
+        dh += dhr * dhr + dhi * dhi;
+        de += der * der + dei * dei;
+    }
+    __device__ __forceinline__ void finish(double (&acc)[INV_NPART], double w, double bx, double bz,
+                                           const PropParams& pp) const {
+        acc[INV_E1] = w * 0.5 * (pp.mu * h2 + pp.eps * e2);
+        acc[INV_H1] = w * ((bx * chx + chy + bz * chz) * pp.inv_eps + (bx * cex + cey + bz * cez) * pp.inv_mu);
+        acc[INV_M1X] = w * bx * q;
+        acc[INV_M1Y] = w * qy;
+        acc[INV_M1Z] = w * bz * q;
+        acc[INV_DIVH] = w * pp.mu * pp.mu * dh;
+        acc[INV_DIVE] = w * pp.eps * pp.eps * de;
+        acc[INV_DIVE + 1] = 0.0;
+    }
+};
+
 // Minimum waves per SIMD requested for the fused kernel (caps its register budget).
 #ifndef EIFP_ZWAVES64
 #define EIFP_ZWAVES64 1
@@ -469,7 +615,7 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
     cpx<T>* buf = mem.work;
     const int c = threadIdx.x % B, t = threadIdx.x / B;
     int tx, ty;
-    xcd_tiles(EIFP_FUSED_XCD, tx, ty);
+    xcd_tiles(EIFP_FUSED_XCD, gridDim.x, tx, ty);
     const int col = tx * B + c;
     const int o = ty;
     const bool active = col < M;
@@ -501,6 +647,9 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
 #pragma unroll
     for (int q = 0; q < Q; ++q) acc[q] = 0.0;
     const double w = col == 0 ? 1.0 : 2.0;
+    // basic record along y: per-pencil sums, scaled once (the order of the sums is fixed)
+    constexpr bool kPencil = (Q == INV_NPART && AXIS == 1);
+    PencilSums ps;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         // after a forward transform register i holds position m_last(i); loaded from the
@@ -521,7 +670,10 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
                 e[q] = scale(e[q], s);
             }
         }
-        if (want_inv && active) accumulate_invariants<Q>(acc, w, bx, by, bz, h, e, pp);
+        if (want_inv && active) {
+            if constexpr (kPencil) ps.add(bx, by, bz, h, e);
+            else accumulate_invariants<Q>(acc, w, bx, by, bz, h, e, pp);
+        }
         if (MODE == Z_STEP || MODE == Z_JUMP) {
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
@@ -530,6 +682,9 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
             }
         }
         if (EIFP_FUSED_SB & 2) __builtin_amdgcn_sched_barrier(0);  // one mode's temporaries live at a time
+    }
+    if constexpr (kPencil) {
+        if (want_inv && active) ps.finish(acc, w, bx, bo, pp);
     }
     if (want_inv) block_reduce_store<NT, Q>(acc, mem.partials + ((long)ty * gridDim.x + tx) * Q, s_red);
     if (MODE == Z_STEP || MODE == Z_JUMP) {
@@ -548,77 +703,6 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
     }
 }
 
-// ---------------------------------------------------------------------------------
-// deterministic compensated finalize of the invariant partials
-// ---------------------------------------------------------------------------------
-// Grid: one block per member.  out (member's inv): [0] E1 [1] H1 [2..4] M1
-// [5] ||div~(mu H)||_N [6] ||div~(eps E)||_N; extended record: [8] E2 [9..11] E3
-// [12..14] E4 [15] H2
-__device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
-    const double t = s + x;
-    c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
-    s = t;
-}
-
-// Thread j sums records j, j + 1024, ... (each record: Q contiguous doubles) with
-// Neumaier compensation, then the 1024 (sum, compensation) pairs are combined by a
-// fixed xor-butterfly inside each wave and a fixed loop over the 16 waves: the same
-// partials always give the same bits.
-template <typename T, int Q>
-__global__ void __launch_bounds__(1024) k_finalize(const MemberDesc<T>* __restrict__ md, int nparts) {
-    __shared__ double s_w[16][2 * Q];
-    const double* partials = md[blockIdx.x].partials;
-    double s[Q], c[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) s[q] = c[q] = 0.0;
-#pragma unroll 2
-    for (int j = threadIdx.x; j < nparts; j += 1024) {
-        const double* rec = partials + (long)j * Q;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) neumaier_add(s[q], c[q], rec[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const double os = __shfl_xor(s[q], off, 64), oc = __shfl_xor(c[q], off, 64);
-            c[q] += oc;
-            neumaier_add(s[q], c[q], os);
-        }
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            s_w[wid][q] = s[q];
-            s_w[wid][Q + q] = c[q];
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double res[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            double a = 0.0, ca = 0.0;
-            for (int w = 0; w < 16; ++w) {
-                ca += s_w[w][Q + q];
-                neumaier_add(a, ca, s_w[w][q]);
-            }
-            res[q] = a + ca;
-        }
-        double* out = md[blockIdx.x].inv;
-        out[0] = res[INV_E1];
-        out[1] = res[INV_H1];
-        out[2] = res[INV_M1X];
-        out[3] = res[INV_M1Y];
-        out[4] = res[INV_M1Z];
-        out[5] = sqrt(res[INV_DIVH]);
-        out[6] = sqrt(res[INV_DIVE]);
-        out[7] = 0.0;
-#pragma unroll
-        for (int q = INV_NPART; q < Q; ++q) out[q] = res[q];
-    }
-}
 
 // FP64 <-> T conversion for upload / download of the state.
 template <typename TO, typename TI>

@@ -29,9 +29,12 @@ struct Grid3 {
 template <typename T>
 int launch_x(bool inv, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st);
 
-// single-component C2C along y or z on each member's work buffer (six components, in place)
+// single-component C2C along y or z on each member's work buffer (six components, in
+// place); fin_nparts > 0 also finalizes each member's invariant partials (that many
+// records) in one extra workgroup per member, alongside the transform
 template <typename T>
-int launch_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const void* tw, hipStream_t st);
+int launch_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const void* tw, hipStream_t st,
+               int fin_nparts = 0);
 
 // fused pass along `axis` on each member's work buffer: mode Z_STEP (forward, propagate,
 // partials, inverse, store), Z_FORWARD (forward, partials only; memory untouched),

@@ -96,18 +96,20 @@ int run_x(bool inv, const Grid3& g, const void* md, int nm, const void* twx, hip
 }
 
 template <typename T, int N>
-int run_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const void* tw, hipStream_t st) {
+int run_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const void* tw, hipStream_t st,
+            int fin_nparts) {
     using C = CCfg<T, N>;
     const AxisGeom a = axis_geom(axis, g);
-    const dim3 grid((unsigned)((g.M + C::B - 1) / C::B), (unsigned)a.n_outer, (unsigned)(6 * nm));
+    const unsigned ntx = (unsigned)((g.M + C::B - 1) / C::B) + (fin_nparts > 0 ? 1u : 0u);
+    const dim3 grid(ntx, (unsigned)a.n_outer, (unsigned)(6 * nm));
     const dim3 block(C::P::T * C::B);
     const MemberDesc<T>* d = (const MemberDesc<T>*)md;
     if (inv)
         hipLaunchKernelGGL((k_c2c<T, typename C::P, C::B, true>), grid, block, 0, st, d, g.M, a.pstride, a.ostride,
-                           g.cs(), (const cpx<T>*)tw);
+                           g.cs(), (const cpx<T>*)tw, fin_nparts);
     else
         hipLaunchKernelGGL((k_c2c<T, typename C::P, C::B, false>), grid, block, 0, st, d, g.M, a.pstride, a.ostride,
-                           g.cs(), (const cpx<T>*)tw);
+                           g.cs(), (const cpx<T>*)tw, fin_nparts);
     return check_launch();
 }
 
@@ -162,11 +164,12 @@ int launch_x(bool inv, const Grid3& g, const void* md, int nm, const void* twx, 
 }
 
 template <typename T>
-int launch_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const void* tw, hipStream_t st) {
+int launch_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const void* tw, hipStream_t st,
+               int fin_nparts) {
     switch (axis_len(axis, g)) {
 #define EIFP_CASE(N) \
     case N:          \
-        return run_c2c<T, N>(inv, axis, g, md, nm, tw, st);
+        return run_c2c<T, N>(inv, axis, g, md, nm, tw, st, fin_nparts);
         EIFP_AXIS_SIZES(EIFP_CASE)
 #undef EIFP_CASE
         default:
@@ -212,7 +215,7 @@ int launch_finalize(const void* md, int nm, int nparts, hipStream_t st, bool ext
 
 #define EIFP_INSTANTIATE(T)                                                                                   \
     template int launch_x<T>(bool, const Grid3&, const void*, int, const void*, hipStream_t);                 \
-    template int launch_c2c<T>(bool, int, const Grid3&, const void*, int, const void*, hipStream_t);          \
+    template int launch_c2c<T>(bool, int, const Grid3&, const void*, int, const void*, hipStream_t, int);     \
     template int launch_fused<T>(int, int, const Grid3&, const void*, int, const void*, int, hipStream_t);    \
     template int fused_partial_count<T>(int, const Grid3&);                                                   \
     template int launch_finalize<T>(const void*, int, int, hipStream_t, bool);
