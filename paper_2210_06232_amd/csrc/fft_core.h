@@ -383,14 +383,30 @@ struct LdsCols2 {
     __device__ __forceinline__ void after_load() { cur ^= 1; }
 };
 
-// Rows: P pencils stored one after another with pitch LD.
+// Rows: P pencils stored one after another with pitch LD (at least rows_pitch<T>(M)),
+// with one pad element after every 2^skew positions, so that positions a power of two
+// apart (the stride of the first exchange) spread over the banks.  Measured best: every
+// 8 in FP64, every 16 in FP32.
+#ifndef EIFP_XSKEW64
+#define EIFP_XSKEW64 3
+#endif
+#ifndef EIFP_XSKEW32
+#define EIFP_XSKEW32 4
+#endif
+template <typename T> struct RowSkew { static constexpr int value = sizeof(T) == 8 ? EIFP_XSKEW64 : EIFP_XSKEW32; };
+template <typename T>
+__host__ __device__ constexpr int rows_pitch(int m) { return m + 1 + (RowSkew<T>::value ? m >> RowSkew<T>::value : 0); }
 template <typename T, int LD>
 struct LdsRows {
     T* re;
     T* im;
     int p;
-    __device__ __forceinline__ void st(int pos, cpx<T> a) { re[p * LD + pos] = a.x; im[p * LD + pos] = a.y; }
-    __device__ __forceinline__ cpx<T> ld(int pos) const { return {re[p * LD + pos], im[p * LD + pos]}; }
+    static __device__ __forceinline__ int at(int pos) {
+        constexpr int sk = RowSkew<T>::value;
+        return sk ? pos + (pos >> sk) : pos;
+    }
+    __device__ __forceinline__ void st(int pos, cpx<T> a) { re[p * LD + at(pos)] = a.x; im[p * LD + at(pos)] = a.y; }
+    __device__ __forceinline__ cpx<T> ld(int pos) const { return {re[p * LD + at(pos)], im[p * LD + at(pos)]}; }
     __device__ __forceinline__ void sync() { __syncthreads(); }
     __device__ __forceinline__ void after_load() { __syncthreads(); }
 };

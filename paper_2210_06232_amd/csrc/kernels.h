@@ -66,12 +66,20 @@ __device__ __forceinline__ double omega(int m, int n, double nu) {
 // ---------------------------------------------------------------------------------
 // x pass: real <-> packed half spectrum along contiguous rows
 // ---------------------------------------------------------------------------------
+// Pass order through the state (EIFP_MALL_ORDER = 1): each pass starts with the data the
+// pass before it wrote last, which is still in the 256 MB last-level cache.  x forward
+// ascending rows -> z forward descending components -> fused y (reads every component
+// of a tile) -> z inverse ascending components -> x inverse descending rows -> (next
+// step) x forward ascending rows.
+#ifndef EIFP_MALL_ORDER
+#define EIFP_MALL_ORDER 1
+#endif
 // twx[k] = exp(-2 pi i k / Nx), k < Nx (the length-M FFT reads every second entry).
 // Grid: (row blocks, members).  Forward reads state, writes work.
 template <typename T, class P, int NP>
 __global__ void __launch_bounds__(P::T * NP)
 k_x_fwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restrict__ twx) {
-    constexpr int M = P::N, E = P::E, TT = P::T, LD = M + 1;
+    constexpr int M = P::N, E = P::E, TT = P::T, LD = rows_pitch<T>(M);
     __shared__ T s_re[NP * LD];
     __shared__ T s_im[NP * LD];
     __shared__ cpx<T> s_tw[2 * M * TwParts<T>::value];
@@ -115,7 +123,7 @@ k_x_fwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
 template <typename T, class P, int NP>
 __global__ void __launch_bounds__(P::T * NP)
 k_x_inv(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restrict__ twx) {
-    constexpr int M = P::N, E = P::E, TT = P::T, LD = M + 1;
+    constexpr int M = P::N, E = P::E, TT = P::T, LD = rows_pitch<T>(M);
     __shared__ T s_re[NP * LD];
     __shared__ T s_im[NP * LD];
     __shared__ cpx<T> s_tw[2 * M * TwParts<T>::value];
@@ -123,8 +131,10 @@ k_x_inv(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
     const cpx<T>* src = md[blockIdx.y].work;
     cpx<T>* dst = md[blockIdx.y].state;
     const int t = threadIdx.x % TT, p = threadIdx.x / TT;
-    const long row = (long)blockIdx.x * NP + p;
-    const bool active = row < nrows;
+    // rows in descending order (EIFP_MALL_ORDER): the z inverse pass wrote the last
+    // components last, and those are the ones still in the last-level cache
+    const long row = EIFP_MALL_ORDER ? nrows - 1 - ((long)blockIdx.x * NP + p) : (long)blockIdx.x * NP + p;
+    const bool active = row >= 0 && row < nrows;
     const cpx<T>* in = src + (active ? row : nrows - 1) * M;
     LdsRows<T, LD> lds{s_re, s_im, p};
     cpx<T> v[E];
@@ -318,7 +328,11 @@ k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, l
     xcd_tiles(EIFP_C2C_XCD, nxt, tx, ty);
     const int col = tx * B + c;
     const int o = ty;
-    const int member = blockIdx.z / 6, comp = blockIdx.z % 6;
+    // the forward pass takes the components in descending order (EIFP_MALL_ORDER): the x
+    // pass before it wrote the last components last, and those are still in the
+    // last-level cache; the inverse keeps ascending order (so the x inverse after it
+    // starts from the last component)
+    const int member = blockIdx.z / 6, comp = (EIFP_MALL_ORDER && !INV) ? 5 - (int)(blockIdx.z % 6) : blockIdx.z % 6;
     const bool active = col < M;
     const __amdgpu_buffer_rsrc_t r = make_rsrc(md[member].work + comp * cs, (unsigned)(cs * sizeof(cpx<T>)));
     const unsigned voff = (unsigned)(t * pstride + o * ostride + (active ? col : M - 1)) * sizeof(cpx<T>);

@@ -34,7 +34,7 @@ constexpr int pow2floor(int a) {  // largest power of two <= a (a >= 1)
 
 template <typename T, int M> struct XCfg {
     using P = Plan<M, XYE<M>::E>;
-    static constexpr int NP = cmax(1, cmin(256 / P::T, (48 * 1024) / ((M + 1) * 2 * (int)sizeof(T))));
+    static constexpr int NP = cmax(1, cmin(256 / P::T, (48 * 1024) / (rows_pitch<T>(M) * 2 * (int)sizeof(T))));
 };
 
 // Row segment (bytes along x) of a tile of the single-component strided pass.
