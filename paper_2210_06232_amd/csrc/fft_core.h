@@ -270,6 +270,11 @@ __host__ __device__ constexpr int m_last(int idx) {
 // Runs stages s..S-1.  v holds stage-s inputs: v[u R + r] = x[j + r N/R], j = t + T u.
 // tw[k * TWS] = exp(-2 pi i k / N) for k < N (forward table; conj for the inverse).
 // Lds provides st(pos, v), ld(pos) for this thread's pencil and sync().
+// Stage twiddles come from tw[k * TWS] = exp(-2 pi i k / N), or, with TWS = kStagedTw,
+// from a table in the plan's stage order (stage_table_plan), where the R - 1 factors of
+// stage s for butterfly j are entries (NS - R_0) + (r - 1) NS + j mod NS: the lanes of one
+// read then take consecutive entries instead of entries a power of two apart.
+constexpr int kStagedTw = 0;
 template <class P, int s, bool INV, int TWS, bool CT = true, typename T, class Lds>
 __device__ __forceinline__ void fft_stages(cpx<T> (&v)[P::E], int t, Lds& lds, const cpx<T>* __restrict__ tw) {
     constexpr int N = P::N, E = P::E, TT = P::T;
@@ -283,7 +288,10 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[P::E], int t, Lds& lds, c
             const int jm = j % NS;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                v[u * R + r] = twmul<INV, CT>(tw, (jm * r * (N / (NS * R))) * TWS, N * TWS, v[u * R + r]);
+                if constexpr (TWS == kStagedTw)
+                    v[u * R + r] = twmul<INV, CT>(tw, (NS - P::R[0]) + (r - 1) * NS + jm, N, v[u * R + r]);
+                else
+                    v[u * R + r] = twmul<INV, CT>(tw, (jm * r * (N / (NS * R))) * TWS, N * TWS, v[u * R + r]);
             }
         }
         Dft<R, INV, T>::run(&v[u * R]);
@@ -329,6 +337,58 @@ __device__ __forceinline__ void last_to_first(cpx<T> (&v)[P::E]) {
     for (int i = 0; i < P::E; ++i) v[i] = w[i];
 }
 
+// NC pencils of the same thread transformed in lockstep: every exchange moves all NC
+// through LDS behind one synchronisation (Lds::st / ld take the pencil index), so the NC
+// transforms share their barriers and give the scheduler NC independent butterflies.
+template <class P, int s, bool INV, int TWS, bool CT, int NC, typename T, class Lds>
+__device__ __forceinline__ void fft_stages_n(cpx<T> (&v)[NC][P::E], int t, Lds& lds, const cpx<T>* __restrict__ tw) {
+    constexpr int N = P::N, E = P::E, TT = P::T;
+    constexpr int R = P::R[s];
+    constexpr int NS = span_before<P, s>();
+    constexpr int NB = E / R;
+#pragma unroll
+    for (int n = 0; n < NC; ++n) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = t + TT * u;
+            if constexpr (NS > 1) {
+                const int jm = j % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    if constexpr (TWS == kStagedTw)
+                        v[n][u * R + r] = twmul<INV, CT>(tw, (NS - P::R[0]) + (r - 1) * NS + jm, N, v[n][u * R + r]);
+                    else
+                        v[n][u * R + r] = twmul<INV, CT>(tw, (jm * r * (N / (NS * R))) * TWS, N * TWS, v[n][u * R + r]);
+                }
+            }
+            Dft<R, INV, T>::run(&v[n][u * R]);
+        }
+    }
+    if constexpr (s + 1 < P::S) {
+        constexpr int R2 = P::R[s + 1];
+#pragma unroll
+        for (int n = 0; n < NC; ++n)
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int j = t + TT * u;
+                const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds.st(n, base + r * NS, v[n][u * R + r]);
+            }
+        lds.sync();
+#pragma unroll
+        for (int n = 0; n < NC; ++n)
+#pragma unroll
+            for (int u = 0; u < E / R2; ++u) {
+                const int j = t + TT * u;
+#pragma unroll
+                for (int r = 0; r < R2; ++r) v[n][u * R2 + r] = lds.ld(n, j + r * (N / R2));
+            }
+        lds.after_load();
+        fft_stages_n<P, s + 1, INV, TWS, CT, NC>(v, t, lds, tw);
+    }
+}
+
 template <class P, bool INV, int TWS, bool CT = true, typename T, class Lds>
 __device__ __forceinline__ void fft_pencil(cpx<T> (&v)[P::E], int t, Lds& lds, const cpx<T>* __restrict__ tw) {
     fft_stages<P, 0, INV, TWS, CT>(v, t, lds, tw);
@@ -348,36 +408,86 @@ __host__ __device__ constexpr int col_pitch(int B) { return B + EIFP_LDS_PAD; }
 #define EIFP_ZPAD 0
 #endif
 __host__ __device__ constexpr int zcol_pitch(int B) { return B + EIFP_ZPAD; }
+// rows of a [pos][col] buffer with one empty row after every 2^SK positions (SK > 0)
+template <int N, int SK>
+__host__ __device__ constexpr int skew_rows() { return N + (SK > 0 ? (N >> SK) + 1 : 0); }
+// skew of the fused pass's exchange rows (see LdsCols2): power-of-two lengths and
+// lengths with a factor 3
+#ifndef EIFP_ZSKEW
+#define EIFP_ZSKEW 1
+#endif
+#ifndef EIFP_ZSKEW3
+#define EIFP_ZSKEW3 0
+#endif
+// (EIFP_ZSKEW = 1 selects log2 of the plan's first radix: the stage-0 writes of one
+// register are that radix apart)
+template <class P>
+__host__ __device__ constexpr int zskew() {
+    if (P::N % 3 == 0) return EIFP_ZSKEW3;
+    if (EIFP_ZSKEW != 1) return EIFP_ZSKEW;
+    int k = 0;
+    while ((1 << k) < P::R[0]) ++k;
+    return k;
+}
+template <class P, int B>
+__host__ __device__ constexpr int zplane() { return skew_rows<P::N, zskew<P>()>() * zcol_pitch(B); }
 // after_load(): a single buffer needs a second barrier before it is written again; the
 // double-buffered views flip to the other buffer instead, which is safe because the
 // next write to this buffer comes after the next exchange's barrier.
-template <typename T, int B>
+template <typename T, int B, int PITCH = col_pitch(B), int SK = 0>
 struct LdsCols {
     T* re;
     T* im;
     int c;
-    __device__ __forceinline__ void st(int pos, cpx<T> a) { re[pos * col_pitch(B) + c] = a.x; im[pos * col_pitch(B) + c] = a.y; }
-    __device__ __forceinline__ cpx<T> ld(int pos) const { return {re[pos * col_pitch(B) + c], im[pos * col_pitch(B) + c]}; }
+    static __device__ __forceinline__ int at(int pos) { return (SK > 0 ? pos + (pos >> SK) : pos) * PITCH; }
+    __device__ __forceinline__ void st(int pos, cpx<T> a) { re[at(pos) + c] = a.x; im[at(pos) + c] = a.y; }
+    __device__ __forceinline__ cpx<T> ld(int pos) const { return {re[at(pos) + c], im[at(pos) + c]}; }
     __device__ __forceinline__ void sync() { __syncthreads(); }
     __device__ __forceinline__ void after_load() { __syncthreads(); }
 };
 
 // Two alternating [pos][col] buffers of PLANE reals per plane (re, im): one barrier per
-// exchange.  base holds re0, im0, re1, im1.
-template <typename T, int B, int PLANE, int PITCH = col_pitch(B)>
+// exchange.  base holds re0, im0, re1, im1.  With SK > 0 one empty row follows every 2^SK
+// positions (row pos + (pos >> SK)): the stage-0 writes, whose positions are 8 apart for
+// a fixed register, then fall in different banks, and the offsets between a thread's
+// accesses stay compile-time constants.
+template <typename T, int B, int PLANE, int PITCH = col_pitch(B), int SK = 0>
 struct LdsCols2 {
     T* base;
     int c;
     int cur;
+    static __device__ __forceinline__ int row(int pos) { return SK > 0 ? pos + (pos >> SK) : pos; }
     __device__ __forceinline__ T* re() const { return base + (2 * cur) * PLANE; }
     __device__ __forceinline__ void st(int pos, cpx<T> a) {
         T* r = re();
-        r[pos * PITCH + c] = a.x;
-        r[PLANE + pos * PITCH + c] = a.y;
+        r[row(pos) * PITCH + c] = a.x;
+        r[PLANE + row(pos) * PITCH + c] = a.y;
     }
     __device__ __forceinline__ cpx<T> ld(int pos) const {
         const T* r = re();
-        return {r[pos * PITCH + c], r[PLANE + pos * PITCH + c]};
+        return {r[row(pos) * PITCH + c], r[PLANE + row(pos) * PITCH + c]};
+    }
+    __device__ __forceinline__ void sync() { __syncthreads(); }
+    __device__ __forceinline__ void after_load() { cur ^= 1; }
+};
+
+// NC pencil sets in two alternating buffers: [buffer][set][re, im][PLANE reals], rows
+// skewed as in LdsCols2; one barrier per exchange.
+template <typename T, int B, int PLANE, int PITCH, int SK, int NC>
+struct LdsColsN {
+    T* base;
+    int c;
+    int cur;
+    static __device__ __forceinline__ int row(int pos) { return SK > 0 ? pos + (pos >> SK) : pos; }
+    __device__ __forceinline__ T* re(int n) const { return base + (2 * (cur * NC + n)) * PLANE; }
+    __device__ __forceinline__ void st(int n, int pos, cpx<T> a) {
+        T* r = re(n);
+        r[row(pos) * PITCH + c] = a.x;
+        r[PLANE + row(pos) * PITCH + c] = a.y;
+    }
+    __device__ __forceinline__ cpx<T> ld(int n, int pos) const {
+        const T* r = re(n);
+        return {r[row(pos) * PITCH + c], r[PLANE + row(pos) * PITCH + c]};
     }
     __device__ __forceinline__ void sync() { __syncthreads(); }
     __device__ __forceinline__ void after_load() { cur ^= 1; }
@@ -418,6 +528,22 @@ template <typename T>
 __device__ __forceinline__ void stage_table(cpx<T>* dst, const cpx<T>* __restrict__ src, int n) {
     // n entries, plus their lo parts for FP32 tables
     for (int i = threadIdx.x; i < n * TwParts<T>::value; i += blockDim.x) dst[i] = src[i];
+}
+
+// The stage-ordered table of plan P (N - 1 entries, then their lo parts at +N for FP32)
+// from the plain table src[k] = exp(-2 pi i k / N); the caller synchronises before use.
+template <class P, int s = 1, typename T>
+__device__ __forceinline__ void stage_table_plan(cpx<T>* dst, const cpx<T>* __restrict__ src) {
+    if constexpr (s < P::S) {
+        constexpr int N = P::N, R = P::R[s], NS = span_before<P, s>(), off = NS - P::R[0];
+        for (int i = threadIdx.x; i < NS * (R - 1); i += blockDim.x) {
+            const int r = i / NS + 1, jm = i % NS;
+            const int k = jm * r * (N / (NS * R));
+            dst[off + i] = src[k];
+            if constexpr (TwParts<T>::value == 2) dst[N + off + i] = src[N + k];
+        }
+        stage_table_plan<P, s + 1>(dst, src);
+    }
 }
 
 // Raw buffer access (gfx9 descriptor): one SGPR descriptor per array, a per-lane VGPR

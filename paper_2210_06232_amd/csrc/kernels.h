@@ -14,7 +14,9 @@
 //   y pass   fused: C2C along y for all six components of a tile, the mode-wise
 //            exponential propagator (Prop. 2.1/2.2, Alg. 2 step 4) with the 1/(Nx Ny Nz)
 //            of the inverse transform folded in, the invariant partial sums, and the
-//            inverse C2C along y.
+//            inverse C2C along y.  Powers of two: one thread holds all six components
+//            (k_fused; persistent workgroups in FP64, components transformed in pairs);
+//            lengths with a factor 3: two thread groups hold H and E (k_fused_split).
 //   z^-1, x^-1 as above in reverse (complex-to-real merge back).
 //
 // Every kernel works on a batch of solves of one shape ("members"): the member index
@@ -305,6 +307,22 @@ __device__ __forceinline__ void xcd_tiles(bool on, unsigned nxt, int& tx, int& t
 // column, whose workgroup at outer index 0 and component 0 finalizes its member's
 // invariant partials (fin_nparts records) while the other workgroups transform: the
 // partials were written by the preceding fused pass, and the next one runs after this.
+// The strided pass's exchange: unpadded rows skewed every 2^EIFP_CSKEW positions
+// (EIFP_CSKEW = 1: log2 of the plan's first radix; 0: rows padded by EIFP_LDS_PAD), and
+// stage twiddles in the plan's stage order (EIFP_C2C_STW).
+#ifndef EIFP_CSKEW
+#define EIFP_CSKEW 0
+#endif
+#ifndef EIFP_C2C_STW
+#define EIFP_C2C_STW 1
+#endif
+template <class P>
+__host__ __device__ constexpr int c2c_skew() {
+    if (EIFP_CSKEW != 1) return EIFP_CSKEW;
+    int k = 0;
+    while ((1 << k) < P::R[0]) ++k;
+    return k;
+}
 template <typename T, class P, int B, bool INV>
 __global__ void __launch_bounds__(P::T * B)
 k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, long cs,
@@ -319,10 +337,12 @@ k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, l
         }
         return;
     }
-    __shared__ T s_re[NP * col_pitch(B)];
-    __shared__ T s_im[NP * col_pitch(B)];
+    constexpr int SK = c2c_skew<P>(), PITCH = SK > 0 ? B : col_pitch(B), ROWS = skew_rows<NP, SK>();
+    __shared__ T s_re[ROWS * PITCH];
+    __shared__ T s_im[ROWS * PITCH];
     __shared__ cpx<T> s_tw[NP * TwParts<T>::value];
-    stage_table(s_tw, tw, NP);
+    if (EIFP_C2C_STW) stage_table_plan<P>(s_tw, tw);
+    else stage_table(s_tw, tw, NP);
     const int c = threadIdx.x % B, t = threadIdx.x / B;
     int tx, ty;
     xcd_tiles(EIFP_C2C_XCD, nxt, tx, ty);
@@ -339,8 +359,8 @@ k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, l
     const unsigned sstep = (unsigned)(TT * pstride) * sizeof(cpx<T>);
     cpx<T> v[E];
     load_col<T, P>(v, r, voff, sstep);
-    LdsCols<T, B> lds{s_re, s_im, c};
-    fft_pencil<P, INV, 1>(v, t, lds, s_tw);
+    LdsCols<T, B, PITCH, SK> lds{s_re, s_im, c};
+    fft_pencil<P, INV, EIFP_C2C_STW ? kStagedTw : 1>(v, t, lds, s_tw);
     store_col<T, P>(v, r, voff, sstep, active);
 }
 
@@ -612,22 +632,334 @@ template <typename T, int N> struct ZWaves {
 // The fused pass transforms, propagates and transforms back along one strided axis.
 // AXIS = 1: pencils along y (stride M), one tile row per z index; AXIS = 2: pencils along
 // z (stride Ny M), one tile row per y index.  Strides in complex elements; cs is the
-// component stride.  Grid: (x tiles, outer, members); each block writes one partial
-// record, at index (tile row) * gridDim.x + (tile column) of its member's partials.
+// component stride.  The ntx x n_outer tiles of a member are shared by gridDim.x
+// workgroups (grid: (G, 1, members)), each taking tiles in turn (persist_tile); the
+// loads of a workgroup's next tile are issued component by component as the inverse
+// transforms of the current tile store theirs, into the registers just freed, so they
+// overlap the rest of the tile's work.  Each workgroup writes one partial record, at
+// index blockIdx.x of its member's partials, summed over its tiles in a fixed order.
+//
+// Tile of work item k of workgroup g: the dispatcher deals workgroups to the 8 XCDs
+// round robin, so with G a multiple of 8 the workgroups of one XCD take a contiguous
+// block of G/8 tiles at every k (neighbouring tiles share cache lines).
+__device__ __forceinline__ int persist_tile(int k, int G) {
+    const int g = (int)blockIdx.x;
+    if ((G & 7) != 0 || !EIFP_FUSED_XCD) return k * G + g;
+    return k * G + (g & 7) * (G >> 3) + (g >> 3);
+}
+
+// Persistent workgroups (with the prefetch of the next tile) in FP64; in FP32 the loop's
+// extra live registers spill at two waves per SIMD, so each workgroup takes one tile.
+#ifndef EIFP_ZPERSIST64
+#define EIFP_ZPERSIST64 1
+#endif
+#ifndef EIFP_ZPERSIST32
+#define EIFP_ZPERSIST32 0
+#endif
+// Components transformed in lockstep by the fused pass (1, 2, 3 or 6): they share each
+// exchange's barrier; their double-buffered exchange takes 4 NC N' B sizeof(T) bytes.
+#ifndef EIFP_ZLOCK64
+#define EIFP_ZLOCK64 2
+#endif
+#ifndef EIFP_ZLOCK32
+#define EIFP_ZLOCK32 2
+#endif
+template <typename T, int N> struct ZLockstep {
+    // (one at a time for lengths with a factor 3, and above 256, where the LDS of two
+    // workgroups per CU would not hold them)
+    static constexpr int value = (N % 3 == 0 || N > 256) ? 1 : (sizeof(T) == 8 ? EIFP_ZLOCK64 : EIFP_ZLOCK32);
+};
+template <typename T> struct ZPersist {
+    static constexpr bool value = sizeof(T) == 8 ? EIFP_ZPERSIST64 != 0 : EIFP_ZPERSIST32 != 0;
+};
+
 template <typename T, class P, int B, int MODE, int AXIS>
 __global__ void __launch_bounds__(P::T * B, (ZWaves<T, P::N>::value))
-k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, long ostride, long cs,
+k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx, long pstride, long ostride, long cs,
         const cpx<T>* __restrict__ tw, int want_inv) {
+    constexpr bool PERSIST = ZPersist<T>::value;
     constexpr int NZ = P::N, E = P::E, TT = P::T, NT = P::T * B;
-    __shared__ T s_x[2 * 2 * NZ * zcol_pitch(B)];
+    constexpr int PLANE = zplane<P, B>();
+    constexpr int NC = ZLockstep<T, P::N>::value;  // components transformed together
+    static_assert(6 % NC == 0, "components in equal groups");
+    __shared__ T s_x[2 * 2 * NC * PLANE];
     __shared__ cpx<T> s_tw[NZ * TwParts<T>::value];
     constexpr int Q = NQ<MODE>::value;
     __shared__ double s_red[((NT + 63) / 64) * Q];
-    stage_table(s_tw, tw, NZ);
+    stage_table_plan<P>(s_tw, tw);  // ordered by stage (conflict-free reads)
     const MemberDesc<T>& mem = md[blockIdx.z];
     const PropParams pp = mem.pp;
     cpx<T>* buf = mem.work;
+    const cpx<T>* src = MODE == Z_JUMP ? mem.spec : buf;
     const int c = threadIdx.x % B, t = threadIdx.x / B;
+    const int G = (int)gridDim.x, ntiles = ntx * n_outer;
+    const unsigned cbytes = (unsigned)cs * sizeof(cpx<T>);
+    const unsigned sstep = (unsigned)(TT * pstride) * sizeof(cpx<T>);
+    LdsColsN<T, B, PLANE, zcol_pitch(B), zskew<P>(), NC> lds{s_x, c, 0};
+    // per-tile geometry: the column, the outer index, and this lane's base offset
+    struct Tile {
+        int col, o;
+        bool active;
+        unsigned voff;
+    };
+    auto tile = [&](int w) {
+        Tile a;
+        a.col = (w % ntx) * B + c;
+        a.o = w / ntx;
+        a.active = a.col < M;
+        a.voff = (unsigned)(t * pstride + a.o * ostride + (a.active ? a.col : M - 1)) * sizeof(cpx<T>);
+        return a;
+    };
+
+    double acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+    int k = 0;
+    int wk = persist_tile(0, G);
+    Tile cur = tile(wk < ntiles ? wk : 0);
+    cpx<T> v[6][E];
+    if (wk < ntiles) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) load_col<T, P>(v[q], make_rsrc(src + q * cs, cbytes), cur.voff, sstep);
+    }
+    while (wk < ntiles) {  // uniform over the workgroup
+        if (MODE != Z_JUMP) {
+#pragma unroll
+            for (int q = 0; q < 6; q += NC) {
+                // re-derive the lane indices per group so that LDS addresses are
+                // recomputed (cheap ALU) instead of being kept live across all transforms
+                int tq = t, cq = c;
+                asm volatile("" : "+v"(tq), "+v"(cq));
+                lds.c = cq;
+                fft_stages_n<P, 0, false, kStagedTw, EIFP_FUSED_CT != 0, NC>(
+                    reinterpret_cast<cpx<T>(&)[NC][E]>(v[q]), tq, lds, s_tw);
+                if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);  // one group's temporaries live at a time
+            }
+        }
+
+        const double bx = cur.col == 0 ? 0.0 : pp.nu[0] * (double)cur.col;  // packed column: Omega_x = 0 at 0 and Nx/2
+        const double bo = omega(cur.o, n_outer, AXIS == 1 ? pp.nu[2] : pp.nu[1]);
+        const double w = cur.col == 0 ? 1.0 : 2.0;
+        const bool sum = want_inv && cur.active;
+        // basic record along y: per-pencil sums, scaled once (the order of the sums is fixed)
+        constexpr bool kPencil = (Q == INV_NPART && AXIS == 1);
+        PencilSums ps;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            // after a forward transform register i holds position m_last(i); loaded from the
+            // anchored spectrum it holds m_first(i), which is also what the inverse expects
+            const int kp = t + TT * (MODE == Z_JUMP ? m_first<P>(i) : m_last<P>(i));
+            const double bp = omega(kp, NZ, AXIS == 1 ? pp.nu[1] : pp.nu[2]);
+            const double by = AXIS == 1 ? bp : bo;
+            const double bz = AXIS == 1 ? bo : bp;
+            cpx<T> h[3] = {v[0][i], v[1][i], v[2][i]};
+            cpx<T> e[3] = {v[3][i], v[4][i], v[5][i]};
+            if (MODE == Z_STEP || MODE == Z_JUMP) {
+                propagate_mode(h, e, bx, by, bz, pp);
+            } else {
+                const T s = (T)pp.inv_ns;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    h[q] = scale(h[q], s);
+                    e[q] = scale(e[q], s);
+                }
+            }
+            if (sum) {
+                if constexpr (kPencil) ps.add(bx, by, bz, h, e);
+                else accumulate_invariants<Q>(acc, w, bx, by, bz, h, e, pp);
+            }
+            if (MODE == Z_STEP || MODE == Z_JUMP) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    v[q][i] = h[q];
+                    v[3 + q][i] = e[q];
+                }
+            }
+            if (EIFP_FUSED_SB & 2) __builtin_amdgcn_sched_barrier(0);  // one mode's temporaries live at a time
+        }
+        if constexpr (kPencil) {
+            if (sum) {
+                double a[INV_NPART];
+                ps.finish(a, w, bx, bo, pp);
+#pragma unroll
+                for (int q = 0; q < INV_NPART; ++q) acc[q] += a[q];
+            }
+        }
+
+        ++k;
+        const int wn = PERSIST ? persist_tile(k, G) : ntiles;
+        const bool more = PERSIST && wn < ntiles;
+        const Tile nxt = tile(more ? wn : wk);
+        if (MODE == Z_STEP || MODE == Z_JUMP) {
+            // inverse transform and store each component as soon as it is done, then
+            // start loading the same component of the next tile into its registers
+#pragma unroll
+            for (int q = 0; q < 6; q += NC) {
+#pragma unroll
+                for (int n = 0; n < NC; ++n)
+                    if (MODE == Z_STEP) last_to_first<P>(v[q + n]);
+                int tq = t, cq = c;
+                asm volatile("" : "+v"(tq), "+v"(cq));
+                lds.c = cq;
+                fft_stages_n<P, 0, true, kStagedTw, EIFP_FUSED_CT != 0, NC>(
+                    reinterpret_cast<cpx<T>(&)[NC][E]>(v[q]), tq, lds, s_tw);
+#pragma unroll
+                for (int n = 0; n < NC; ++n) {
+                    store_col<T, P>(v[q + n], make_rsrc(buf + (q + n) * cs, cbytes), cur.voff, sstep, cur.active);
+                    if (more) load_col<T, P>(v[q + n], make_rsrc(src + (q + n) * cs, cbytes), nxt.voff, sstep);
+                }
+                if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
+            }
+        } else if (more) {
+            // Z_FORWARD leaves memory untouched
+#pragma unroll
+            for (int q = 0; q < 6; ++q) load_col<T, P>(v[q], make_rsrc(src + q * cs, cbytes), nxt.voff, sstep);
+        }
+        wk = wn;
+        cur = nxt;
+    }
+    if (want_inv) block_reduce_store<NT, Q>(acc, mem.partials + (long)blockIdx.x * Q, s_red);
+}
+
+// ---------------------------------------------------------------------------------
+// fused pass, split form: the tile is held by two thread groups of NG = T B threads;
+// group 0 transforms the H components (0-2), group 1 the E components (3-5), so each
+// thread holds 3 E values instead of 6 E and twice the waves fit in the register file.
+// Between the transforms the two partners of a pencil position (same column and thread
+// index t, one in each group, NG threads apart) trade halves through LDS: group 0 takes
+// the modes of register slots [0, E/2) of all six components, group 1 the slots
+// [E/2, E); each propagates its modes and accumulates their invariant sums, and the
+// partners trade back before the inverse transforms.
+// ---------------------------------------------------------------------------------
+#ifndef EIFP_ZSWAVES64
+#define EIFP_ZSWAVES64 2
+#endif
+#ifndef EIFP_ZSWAVES32
+#define EIFP_ZSWAVES32 3
+#endif
+template <typename T, class P> struct ZWavesS {
+    // FP32 lengths with a factor 3 hold 12 values per thread: two waves
+    static constexpr int value = sizeof(T) == 8 ? EIFP_ZSWAVES64 : (P::N % 3 == 0 ? 2 : EIFP_ZSWAVES32);
+};
+
+// swap area: [slot][thread] reals, slot-major so that consecutive threads use
+// consecutive banks; a complex slot k occupies real slots 2k (re) and 2k + 1 (im)
+template <typename T, int NT>
+__device__ __forceinline__ void swap_put(T* sw, int slot, cpx<T> a) {
+    sw[(2 * slot) * NT + threadIdx.x] = a.x;
+    sw[(2 * slot + 1) * NT + threadIdx.x] = a.y;
+}
+template <typename T, int NT>
+__device__ __forceinline__ cpx<T> swap_get(const T* sw, int slot, int from) {
+    return {sw[(2 * slot) * NT + from], sw[(2 * slot + 1) * NT + from]};
+}
+
+// The work of one group (G = 0: H, 1: E) between the transforms; G is a template
+// parameter so that every register index is a compile-time constant.  The callers
+// branch on the group, which is uniform per wave, and keep every barrier outside.
+template <typename T, class P, int MODE, int AXIS, int G, int NT>
+struct SplitHalf {
+    static constexpr int E = P::E, EH = E / 2, TT = P::T, NZ = P::N;
+    static constexpr int KEEP = G * EH;       // register slots this group keeps
+    static constexpr int SEND = EH - KEEP;    // and the ones it hands to its partner
+
+    static __device__ __forceinline__ void put(const cpx<T> (&v)[3][E], T* sw) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int j = 0; j < EH; ++j) swap_put<T, NT>(sw, q * EH + j, v[q][SEND + j]);
+    }
+
+    // fetch the partner's components of the kept modes into o, propagate (or scale) the
+    // kept modes of all six components, accumulate their invariant sums into acc
+    template <int Q>
+    static __device__ __forceinline__ void modes(cpx<T> (&v)[3][E], cpx<T> (&o)[3][EH], const T* sw, int partner,
+                                                 int t, double bx, double bo, double w, bool sum,
+                                                 const PropParams& pp, double (&acc)[Q]) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int j = 0; j < EH; ++j) o[q][j] = swap_get<T, NT>(sw, q * EH + j, partner);
+        constexpr bool kPencil = (Q == INV_NPART && AXIS == 1);
+        PencilSums ps;
+#pragma unroll
+        for (int j = 0; j < EH; ++j) {
+            const int i = KEEP + j;
+            const int kp = t + TT * (MODE == Z_JUMP ? m_first<P>(i) : m_last<P>(i));
+            const double bp = omega(kp, NZ, AXIS == 1 ? pp.nu[1] : pp.nu[2]);
+            const double by = AXIS == 1 ? bp : bo;
+            const double bz = AXIS == 1 ? bo : bp;
+            cpx<T> h[3], e[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                h[q] = G == 0 ? v[q][i] : o[q][j];
+                e[q] = G == 0 ? o[q][j] : v[q][i];
+            }
+            if (MODE == Z_STEP || MODE == Z_JUMP) {
+                propagate_mode(h, e, bx, by, bz, pp);
+            } else {
+                const T s = (T)pp.inv_ns;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    h[q] = scale(h[q], s);
+                    e[q] = scale(e[q], s);
+                }
+            }
+            if (sum) {
+                if constexpr (kPencil) ps.add(bx, by, bz, h, e);
+                else accumulate_invariants<Q>(acc, w, bx, by, bz, h, e, pp);
+            }
+            if (MODE == Z_STEP || MODE == Z_JUMP) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    v[q][i] = G == 0 ? h[q] : e[q];
+                    o[q][j] = G == 0 ? e[q] : h[q];
+                }
+            }
+            if (EIFP_FUSED_SB & 2) __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (kPencil) {
+            if (sum) ps.finish(acc, w, bx, bo, pp);
+        }
+    }
+
+    // hand the partner's propagated components back, and take this group's
+    static __device__ __forceinline__ void put_back(const cpx<T> (&o)[3][EH], T* sw) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int j = 0; j < EH; ++j) swap_put<T, NT>(sw, q * EH + j, o[q][j]);
+    }
+    static __device__ __forceinline__ void get_back(cpx<T> (&v)[3][E], const T* sw, int partner) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int j = 0; j < EH; ++j) v[q][SEND + j] = swap_get<T, NT>(sw, q * EH + j, partner);
+    }
+};
+
+// Same launch geometry and partial records as k_fused, with 2 T B threads per block.
+template <typename T, class P, int B, int MODE, int AXIS>
+__global__ void __launch_bounds__(2 * P::T * B, (ZWavesS<T, P>::value))
+k_fused_split(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, long ostride, long cs,
+              const cpx<T>* __restrict__ tw, int want_inv) {
+    constexpr int NZ = P::N, E = P::E, TT = P::T, NG = P::T * B, NT = 2 * NG, EH = E / 2;
+    constexpr int PLANE = zplane<P, B>();
+    static_assert(NG % 64 == 0, "each group must be whole waves");
+    static_assert(E % 2 == 0, "the modes are split in halves");
+    static_assert(3 * E * NT <= 8 * PLANE, "the swap area fits in the exchange buffers");
+    __shared__ T s_x[8 * PLANE];  // per group: two exchange buffers (re, im); also the swap area
+    __shared__ cpx<T> s_tw[NZ * TwParts<T>::value];
+    constexpr int Q = NQ<MODE>::value;
+    __shared__ double s_red[(NT / 64) * Q];
+    stage_table_plan<P>(s_tw, tw);  // ordered by stage (conflict-free reads)
+    const MemberDesc<T>& mem = md[blockIdx.z];
+    const PropParams pp = mem.pp;
+    cpx<T>* buf = mem.work;
+    const int g = (int)threadIdx.x / NG;  // uniform per wave
+    const int lt = (int)threadIdx.x - g * NG;
+    const int c = lt % B, t = lt / B;
+    const int partner = g ? (int)threadIdx.x - NG : (int)threadIdx.x + NG;
     int tx, ty;
     xcd_tiles(EIFP_FUSED_XCD, gridDim.x, tx, ty);
     const int col = tx * B + c;
@@ -636,87 +968,61 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, 
     const unsigned cbytes = (unsigned)cs * sizeof(cpx<T>);
     const unsigned voff = (unsigned)(t * pstride + o * ostride + (active ? col : M - 1)) * sizeof(cpx<T>);
     const unsigned sstep = (unsigned)(TT * pstride) * sizeof(cpx<T>);
-    LdsCols2<T, B, NZ * zcol_pitch(B), zcol_pitch(B)> lds{s_x, c, 0};
+    LdsCols2<T, B, PLANE, zcol_pitch(B), zskew<P>()> lds{s_x + g * 4 * PLANE, c, 0};
 
-    cpx<T> v[6][E];
-    const cpx<T>* src = MODE == Z_JUMP ? mem.spec : buf;
+    cpx<T> v[3][E];
+    cpx<T>* own = buf + 3 * g * cs;
+    const cpx<T>* src = MODE == Z_JUMP ? mem.spec + 3 * g * cs : own;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) load_col<T, P>(v[q], make_rsrc(src + q * cs, cbytes), voff, sstep);
+    for (int q = 0; q < 3; ++q) load_col<T, P>(v[q], make_rsrc(src + q * cs, cbytes), voff, sstep);
     if (MODE != Z_JUMP) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            // re-derive the lane indices per component so that LDS addresses are
-            // recomputed (cheap ALU) instead of being kept live across all transforms
+        for (int q = 0; q < 3; ++q) {
             int tq = t, cq = c;
             asm volatile("" : "+v"(tq), "+v"(cq));
             lds.c = cq;
-            fft_pencil<P, false, 1, EIFP_FUSED_CT != 0>(v[q], tq, lds, s_tw);
-            if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);  // one component's temporaries live at a time
+            fft_pencil<P, false, kStagedTw, EIFP_FUSED_CT != 0>(v[q], tq, lds, s_tw);
+            if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
         }
     }
 
     const double bx = col == 0 ? 0.0 : pp.nu[0] * (double)col;  // packed column: Omega_x = 0 at 0 and Nx/2
     const double bo = omega(o, n_outer, AXIS == 1 ? pp.nu[2] : pp.nu[1]);
+    const double w = col == 0 ? 1.0 : 2.0;
     double acc[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) acc[q] = 0.0;
-    const double w = col == 0 ? 1.0 : 2.0;
-    // basic record along y: per-pencil sums, scaled once (the order of the sums is fixed)
-    constexpr bool kPencil = (Q == INV_NPART && AXIS == 1);
-    PencilSums ps;
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-        // after a forward transform register i holds position m_last(i); loaded from the
-        // anchored spectrum it holds m_first(i), which is also what the inverse expects
-        const int kp = t + TT * (MODE == Z_JUMP ? m_first<P>(i) : m_last<P>(i));
-        const double bp = omega(kp, NZ, AXIS == 1 ? pp.nu[1] : pp.nu[2]);
-        const double by = AXIS == 1 ? bp : bo;
-        const double bz = AXIS == 1 ? bo : bp;
-        cpx<T> h[3] = {v[0][i], v[1][i], v[2][i]};
-        cpx<T> e[3] = {v[3][i], v[4][i], v[5][i]};
-        if (MODE == Z_STEP || MODE == Z_JUMP) {
-            propagate_mode(h, e, bx, by, bz, pp);
-        } else {
-            const T s = (T)pp.inv_ns;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                h[q] = scale(h[q], s);
-                e[q] = scale(e[q], s);
-            }
-        }
-        if (want_inv && active) {
-            if constexpr (kPencil) ps.add(bx, by, bz, h, e);
-            else accumulate_invariants<Q>(acc, w, bx, by, bz, h, e, pp);
-        }
-        if (MODE == Z_STEP || MODE == Z_JUMP) {
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                v[q][i] = h[q];
-                v[3 + q][i] = e[q];
-            }
-        }
-        if (EIFP_FUSED_SB & 2) __builtin_amdgcn_sched_barrier(0);  // one mode's temporaries live at a time
-    }
-    if constexpr (kPencil) {
-        if (want_inv && active) ps.finish(acc, w, bx, bo, pp);
-    }
+    const bool sum = want_inv && active;
+    using H0 = SplitHalf<T, P, MODE, AXIS, 0, NT>;
+    using H1 = SplitHalf<T, P, MODE, AXIS, 1, NT>;
+    cpx<T> oth[3][EH];
+    __syncthreads();  // every exchange of the forward transforms has been read
+    if (g == 0) H0::put(v, s_x);
+    else H1::put(v, s_x);
+    __syncthreads();
+    if (g == 0) H0::template modes<Q>(v, oth, s_x, partner, t, bx, bo, w, sum, pp, acc);
+    else H1::template modes<Q>(v, oth, s_x, partner, t, bx, bo, w, sum, pp, acc);
     if (want_inv) block_reduce_store<NT, Q>(acc, mem.partials + ((long)ty * gridDim.x + tx) * Q, s_red);
     if (MODE == Z_STEP || MODE == Z_JUMP) {
-        // inverse transform and store each component as soon as it is done; Z_FORWARD
-        // leaves memory untouched
+        __syncthreads();  // the swap area has been read
+        if (g == 0) H0::put_back(oth, s_x);
+        else H1::put_back(oth, s_x);
+        __syncthreads();
+        if (g == 0) H0::get_back(v, s_x, partner);
+        else H1::get_back(v, s_x, partner);
+        __syncthreads();  // before the inverse transforms reuse the area as exchange buffers
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
+        for (int q = 0; q < 3; ++q) {
             if (MODE == Z_STEP) last_to_first<P>(v[q]);
             int tq = t, cq = c;
             asm volatile("" : "+v"(tq), "+v"(cq));
             lds.c = cq;
-            fft_pencil<P, true, 1, EIFP_FUSED_CT != 0>(v[q], tq, lds, s_tw);
-            store_col<T, P>(v[q], make_rsrc(buf + q * cs, cbytes), voff, sstep, active);
+            fft_pencil<P, true, kStagedTw, EIFP_FUSED_CT != 0>(v[q], tq, lds, s_tw);
+            store_col<T, P>(v[q], make_rsrc(own + q * cs, cbytes), voff, sstep, active);
             if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
-
 
 // FP64 <-> T conversion for upload / download of the state.
 template <typename TO, typename TI>

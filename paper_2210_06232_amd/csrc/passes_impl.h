@@ -9,7 +9,8 @@ namespace eifp {
 template <int N> struct XYE { static constexpr int E = (N % 3 == 0) ? (N >= 12 ? 12 : N) : (N >= 16 ? 16 : N); };
 // values per thread for the fused pass, which holds six components at once: 8 in FP64,
 // with one wave per SIMD and the accumulation registers as the overflow of the six
-// pencils; 8 in FP32 at two waves per SIMD; lengths with a factor 3 below
+// pencils; 8 in FP32 at two waves per SIMD; lengths with a factor 3 below (their
+// split form holds three components per thread)
 #ifndef EIFP_ZE64
 #define EIFP_ZE64 8
 #endif
@@ -18,8 +19,7 @@ template <int N> struct XYE { static constexpr int E = (N % 3 == 0) ? (N >= 12 ?
 #endif
 template <typename T, int N> struct ZE {
     static constexpr int E2 = sizeof(T) == 8 ? EIFP_ZE64 : EIFP_ZE32;  // for powers of two
-    // lengths with a factor 3: 6 per thread in FP64, 12 in FP32 (fewer stages), both at
-    // one wave per SIMD
+    // lengths with a factor 3: 6 per thread in FP64, 12 in FP32 (fewer stages)
     static constexpr int E3 = sizeof(T) == 8 ? 6 : 12;
     static constexpr int E = (N % 3 == 0) ? (N >= E3 ? E3 : N) : (N >= E2 ? E2 : N);
 };
@@ -47,7 +47,8 @@ template <typename T, int N> struct CCfg {
     // at most 1024 threads and 80 KB of LDS ([pos][col] pitch B + pad, two planes), a
     // power of two so that tiles stay aligned to the row segments
     static constexpr int B = pow2floor(
-        cmax(1, cmin(cmin(B0, 1024 / P::T), (80 * 1024) / (N * 2 * (int)sizeof(T)) - EIFP_LDS_PAD)));
+        cmax(1, cmin(cmin(B0, 1024 / P::T),
+                     (80 * 1024) / (skew_rows<N, c2c_skew<P>()>() * 2 * (int)sizeof(T)) - EIFP_LDS_PAD)));
 };
 
 // Row segment targeted by a tile of the fused pass; its double-buffered exchange takes
@@ -66,7 +67,26 @@ template <typename T, int N> struct ZCfg {
     using P = Plan<N, ZE<T, N>::E>;
     static constexpr int B0 = cmin(64, cmax(EIFP_ZROW_BYTES / (2 * (int)sizeof(T)), EIFP_ZMIN_THREADS / P::T));
     static constexpr int B = pow2floor(
-        cmax(1, cmin(cmin(B0, 1024 / P::T), (96 * 1024) / (N * 4 * (int)sizeof(T)) - EIFP_ZPAD)));
+        cmax(1, cmin(cmin(B0, 1024 / P::T), (96 * 1024) / (skew_rows<N, zskew<P>()>() * 4 * (int)sizeof(T) * ZLockstep<T, N>::value) -
+                         EIFP_ZPAD)));
+};
+
+// The split fused pass (two thread groups per tile, one per field) holds half the
+// registers per thread; each group must be whole waves, so narrow tiles of short
+// pencils are widened to 64 / T columns.  Its exchange buffers take 8 N (B + pad)
+// sizeof(T) bytes of LDS, kept within 120 KB.
+// 0: never; 1: lengths with a factor 3; 2: every length
+#ifndef EIFP_FUSED_SPLIT
+#define EIFP_FUSED_SPLIT 1
+#endif
+template <typename T, int N> struct ZCfgS {
+    using P = Plan<N, ZE<T, N>::E>;
+    static constexpr int Bmin = cmax(1, 64 / P::T);
+    static constexpr int B0 = cmax(Bmin, cmin(64, EIFP_ZROW_BYTES / (2 * (int)sizeof(T))));
+    static constexpr int Bl = pow2floor(cmax(1, (120 * 1024) / (8 * skew_rows<N, zskew<P>()>() * (int)sizeof(T)) - EIFP_ZPAD));
+    static constexpr int B = cmin(cmin(B0, Bl), 512 / P::T);
+    static constexpr bool ok =
+        (EIFP_FUSED_SPLIT == 2 || (EIFP_FUSED_SPLIT == 1 && N % 3 == 0)) && B >= Bmin && P::E % 2 == 0;
 };
 
 inline int check_launch() { return hipGetLastError() == hipSuccess ? kOk : kLaunchFailed; }
@@ -113,14 +133,52 @@ int run_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const vo
     return check_launch();
 }
 
+// Workgroups of the persistent fused pass (one partial record each; one per tile when
+// the precision's pass is not persistent): as many as the device holds at once (CUs times the step kernel's resident workgroups per CU), a
+// multiple of 8 when there are at least 8, at most one per tile.  The residency is
+// queried once per process; without a device (host-only use) every tile gets its own
+// workgroup.  Every mode uses the step kernel's count, so the partial buffers and the
+// finalize agree on it.
+template <typename T, int N, int AXIS>
+int fused_workgroups(const Grid3& g) {
+    using C = ZCfg<T, N>;
+    const int ntiles = ((g.M + C::B - 1) / C::B) * axis_geom(AXIS, g).n_outer;
+    if (!ZPersist<T>::value) return ntiles;
+    static const int resident = [] {
+        int dev = 0, cus = 0, nb = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused<T, typename C::P, C::B, Z_STEP, AXIS>,
+                                                         C::P::T * C::B, 0) != hipSuccess ||
+            cus <= 0 || nb <= 0) {
+            (void)hipGetLastError();  // leave no error behind for the next launch check
+            return 0;
+        }
+        return cus * nb;
+    }();
+    if (resident <= 0 || resident >= ntiles) return ntiles;
+    return resident >= 8 ? resident & ~7 : resident;
+}
+
 template <typename T, int N, int MODE, int AXIS>
 void run_fused_k(const Grid3& g, const void* md, int nm, const void* tw, int want_inv, hipStream_t st) {
-    using C = ZCfg<T, N>;
     const AxisGeom a = axis_geom(AXIS, g);
-    const dim3 grid((unsigned)((g.M + C::B - 1) / C::B), (unsigned)a.n_outer, (unsigned)nm);
-    const dim3 block(C::P::T * C::B);
-    hipLaunchKernelGGL((k_fused<T, typename C::P, C::B, MODE, AXIS>), grid, block, 0, st, (const MemberDesc<T>*)md,
-                       g.M, a.n_outer, a.pstride, a.ostride, g.cs(), (const cpx<T>*)tw, want_inv);
+    if constexpr (ZCfgS<T, N>::ok) {
+        using C = ZCfgS<T, N>;
+        const dim3 grid((unsigned)((g.M + C::B - 1) / C::B), (unsigned)a.n_outer, (unsigned)nm);
+        const dim3 block(2 * C::P::T * C::B);
+        hipLaunchKernelGGL((k_fused_split<T, typename C::P, C::B, MODE, AXIS>), grid, block, 0, st,
+                           (const MemberDesc<T>*)md, g.M, a.n_outer, a.pstride, a.ostride, g.cs(), (const cpx<T>*)tw,
+                           want_inv);
+    } else {
+        using C = ZCfg<T, N>;
+        const int ntx = (g.M + C::B - 1) / C::B;
+        const dim3 grid((unsigned)fused_workgroups<T, N, AXIS>(g), 1u, (unsigned)nm);
+        const dim3 block(C::P::T * C::B);
+        hipLaunchKernelGGL((k_fused<T, typename C::P, C::B, MODE, AXIS>), grid, block, 0, st,
+                           (const MemberDesc<T>*)md, g.M, a.n_outer, ntx, a.pstride, a.ostride, g.cs(),
+                           (const cpx<T>*)tw, want_inv);
+    }
 }
 
 template <typename T, int N>
@@ -139,8 +197,12 @@ int run_fused(int mode, int axis, const Grid3& g, const void* md, int nm, const 
 
 template <typename T, int N>
 int count_fused(int axis, const Grid3& g) {
-    using C = ZCfg<T, N>;
-    return ((g.M + C::B - 1) / C::B) * axis_geom(axis, g).n_outer;
+    if constexpr (ZCfgS<T, N>::ok) {
+        constexpr int B = ZCfgS<T, N>::B;
+        return ((g.M + B - 1) / B) * axis_geom(axis, g).n_outer;
+    } else {
+        return axis == AXIS_Y ? fused_workgroups<T, N, AXIS_Y>(g) : -1;
+    }
 }
 
 // axis lengths compiled for y and z
