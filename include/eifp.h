@@ -118,11 +118,14 @@ eifp_status eifp_jump(eifp_solver *s, double tau, long long nsteps);
 
 /* Same as eifp_step, and also measures each pass with HIP events recorded on the
  * solver's stream around every kernel.  pass_ms[0..5] receive the summed durations in
- * milliseconds of: x-forward (real-to-complex), z-forward, fused y (forward,
- * propagator, invariant partials, inverse), z-inverse (which also finalizes the
- * invariants, in one extra workgroup), x-inverse (complex-to-real), and the gap where a
- * separate finalize would run (kept for layout; near zero).  Synchronises the stream
- * before returning.  Errors as eifp_step, plus INVALID_ARG for NULL pass_ms. */
+ * milliseconds of: x-forward (real-to-complex; only the first step of the call has a
+ * kernel of its own), z-forward, fused y (forward, propagator, invariant partials,
+ * inverse), z-inverse (which also finalizes the invariants, in one extra workgroup),
+ * x-inverse (complex-to-real; between two steps of the call one kernel does this
+ * step's x-inverse and the next step's x-forward, and its time is counted here), and
+ * the gap where a separate finalize would run (kept for layout; near zero).
+ * Synchronises the stream before returning.  Errors as eifp_step, plus INVALID_ARG for
+ * NULL pass_ms. */
 eifp_status eifp_step_timed(eifp_solver *s, double tau, long long nsteps, double *pass_ms);
 
 /* Invariants of the current state (Sec. 4).  Synchronises the solver's stream.  If no

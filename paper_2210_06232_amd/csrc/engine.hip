@@ -58,7 +58,7 @@ eifp_status run_passes(const Engine& en, int mode, const void* md, int nm, hipSt
                        bool want_inv) {
     int rc;
     if (ev) EIFP_HIP_TRY(hipEventRecord(ev[0], st));
-    if ((rc = launch_x<T>(false, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x forward");
+    if ((rc = launch_x<T>(X_FWD, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x forward");
     if (ev) EIFP_HIP_TRY(hipEventRecord(ev[1], st));
     if ((rc = launch_c2c<T>(false, AXIS_Z, en.g, md, nm, en.twz, st))) return rc_to_status(rc, "z forward");
     if (ev) EIFP_HIP_TRY(hipEventRecord(ev[2], st));
@@ -70,7 +70,7 @@ eifp_status run_passes(const Engine& en, int mode, const void* md, int nm, hipSt
         if ((rc = launch_c2c<T>(true, AXIS_Z, en.g, md, nm, en.twz, st, want_inv ? en.nparts : 0)))
             return rc_to_status(rc, "z inverse");
         if (ev) EIFP_HIP_TRY(hipEventRecord(ev[4], st));
-        if ((rc = launch_x<T>(true, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x inverse");
+        if ((rc = launch_x<T>(X_INV, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x inverse");
         if (ev) EIFP_HIP_TRY(hipEventRecord(ev[5], st));
     } else if (ev) {
         EIFP_HIP_TRY(hipEventRecord(ev[4], st));
@@ -82,10 +82,44 @@ eifp_status run_passes(const Engine& en, int mode, const void* md, int nm, hipSt
     return EIFP_OK;
 }
 
+// nsteps steps.  With work != state, the x inverse of each step but the last and the x
+// forward of the step after it run as one kernel (X_INVFWD), and the z forward pass
+// after it takes the components in ascending order.  Events per step as in run_passes
+// (the x forward slot is empty after the first step; the x inverse slot holds the
+// combined kernel).
+template <typename T>
+eifp_status run_steps(const Engine& en, const void* md, int nm, long long nsteps, hipStream_t st, hipEvent_t* ev,
+                      bool want_inv, bool combine_x) {
+    int rc;
+    for (long long n = 0; n < nsteps; ++n) {
+        hipEvent_t* e = ev ? ev + 7 * n : nullptr;
+        const bool first = n == 0 || !combine_x, last = n + 1 == nsteps || !combine_x;
+        if (e) EIFP_HIP_TRY(hipEventRecord(e[0], st));
+        if (first && (rc = launch_x<T>(X_FWD, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x forward");
+        if (e) EIFP_HIP_TRY(hipEventRecord(e[1], st));
+        if ((rc = launch_c2c<T>(false, AXIS_Z, en.g, md, nm, en.twz, st, 0, first ? 1 : 0)))
+            return rc_to_status(rc, "z forward");
+        if (e) EIFP_HIP_TRY(hipEventRecord(e[2], st));
+        if ((rc = launch_fused<T>(Z_STEP, AXIS_Y, en.g, md, nm, en.twy, want_inv ? 1 : 0, st)))
+            return rc_to_status(rc, "fused y pass");
+        if (e) EIFP_HIP_TRY(hipEventRecord(e[3], st));
+        if ((rc = launch_c2c<T>(true, AXIS_Z, en.g, md, nm, en.twz, st, want_inv ? en.nparts : 0)))
+            return rc_to_status(rc, "z inverse");
+        if (e) EIFP_HIP_TRY(hipEventRecord(e[4], st));
+        if ((rc = launch_x<T>(last ? X_INV : X_INVFWD, en.g, md, nm, en.twx, st)))
+            return rc_to_status(rc, "x inverse");
+        if (e) {
+            EIFP_HIP_TRY(hipEventRecord(e[5], st));
+            EIFP_HIP_TRY(hipEventRecord(e[6], st));
+        }
+    }
+    return EIFP_OK;
+}
+
 template <typename T>
 eifp_status run_spectrum(const Engine& en, const void* md, int nm, hipStream_t st) {
     int rc;
-    if ((rc = launch_x<T>(false, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x forward");
+    if ((rc = launch_x<T>(X_FWD, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x forward");
     if ((rc = launch_c2c<T>(false, AXIS_Z, en.g, md, nm, en.twz, st))) return rc_to_status(rc, "z forward");
     if ((rc = launch_c2c<T>(false, AXIS_Y, en.g, md, nm, en.twy, st))) return rc_to_status(rc, "y forward");
     return EIFP_OK;
@@ -98,7 +132,7 @@ eifp_status run_jump(const Engine& en, const void* md, int nm, hipStream_t st, b
         return rc_to_status(rc, "fused jump pass");
     if ((rc = launch_c2c<T>(true, AXIS_Z, en.g, md, nm, en.twz, st, want_inv ? en.nparts : 0)))
         return rc_to_status(rc, "z inverse");
-    if ((rc = launch_x<T>(true, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x inverse");
+    if ((rc = launch_x<T>(X_INV, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x inverse");
     return EIFP_OK;
 }
 
@@ -203,6 +237,12 @@ eifp_status Engine::passes(int mode, const void* md, int nm, hipStream_t st, hip
 
 eifp_status Engine::forward_spectrum(const void* md, int nm, hipStream_t st) const {
     return prec == EIFP_FP64 ? run_spectrum<double>(*this, md, nm, st) : run_spectrum<float>(*this, md, nm, st);
+}
+
+eifp_status Engine::steps(const void* md, int nm, long long nsteps, hipStream_t st, hipEvent_t* ev, bool want_inv,
+                          bool combine_x) const {
+    return prec == EIFP_FP64 ? run_steps<double>(*this, md, nm, nsteps, st, ev, want_inv, combine_x)
+                             : run_steps<float>(*this, md, nm, nsteps, st, ev, want_inv, combine_x);
 }
 
 eifp_status Engine::jump(const void* md, int nm, hipStream_t st, bool want_inv) const {

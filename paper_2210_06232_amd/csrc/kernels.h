@@ -77,6 +77,63 @@ __device__ __forceinline__ double omega(int m, int n, double nu) {
 #define EIFP_MALL_ORDER 1
 #endif
 // twx[k] = exp(-2 pi i k / Nx), k < Nx (the length-M FFT reads every second entry).
+//
+// Row helpers.  x_forward_row: v holds the row's M complex values (pairs of reals) at
+// positions t + T m_first(i); length-M FFT, then the split
+//   X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W^k (Z[k] - conj Z[M-k]),  W = exp(-2 pi i/Nx),
+// stored to out (X[0] + i X[M] in slot 0).  The LDS rows must be free (every earlier
+// read of them behind a barrier).
+template <typename T, class P, int LD>
+__device__ __forceinline__ void x_forward_row(cpx<T> (&v)[P::E], int t, LdsRows<T, LD>& lds, const cpx<T>* s_tw,
+                                              cpx<T>* out, bool active) {
+    constexpr int M = P::N, E = P::E, TT = P::T;
+    if constexpr (P::S == 1) __syncthreads();  // twiddle table visible before the split
+    fft_pencil<P, false, 2>(v, t, lds, s_tw);
+#pragma unroll
+    for (int i = 0; i < E; ++i) lds.st(t + TT * m_last<P>(i), v[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int k = t + TT * m_last<P>(i);
+        const cpx<T> z = v[i];
+        cpx<T> r;
+        if (k == 0) {
+            r = {z.x + z.y, z.x - z.y};  // X[0] + i X[M]
+        } else {
+            const cpx<T> zc = conj(lds.ld(M - k));
+            const cpx<T> ev = scale(z + zc, (T)0.5);
+            const cpx<T> od = scale(mulmi(z - zc), (T)0.5);  // (Z - conj Z')/(2i)
+            r = ev + twmul<false>(s_tw, k, 2 * M, od);
+        }
+        if (active) out[k] = r;
+    }
+}
+
+// x_inverse_row: v holds the packed half spectrum of a row at positions t + T m_first(i);
+// merge Z[k] = (X[k] + conj X[M-k]) + i W^-k (X[k] - conj X[M-k]) (Z[0] from X[0], X[M]),
+// then the inverse length-M FFT: v ends at positions t + T m_last(i) (the row's reals in
+// pairs, unscaled).
+template <typename T, class P, int LD>
+__device__ __forceinline__ void x_inverse_row(cpx<T> (&v)[P::E], int t, LdsRows<T, LD>& lds, const cpx<T>* s_tw) {
+    constexpr int M = P::N, E = P::E, TT = P::T;
+#pragma unroll
+    for (int i = 0; i < E; ++i) lds.st(t + TT * m_first<P>(i), v[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int k = t + TT * m_first<P>(i);
+        const cpx<T> x = v[i];
+        if (k == 0) {
+            v[i] = {x.x + x.y, x.x - x.y};
+        } else {
+            const cpx<T> xc = conj(lds.ld(M - k));
+            v[i] = (x + xc) + muli(twmul<true>(s_tw, k, 2 * M, x - xc));
+        }
+    }
+    __syncthreads();
+    fft_pencil<P, true, 2>(v, t, lds, s_tw);
+}
+
 // Grid: (row blocks, members).  Forward reads state, writes work.
 template <typename T, class P, int NP>
 __global__ void __launch_bounds__(P::T * NP)
@@ -97,28 +154,14 @@ k_x_fwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = in[t + TT * m_first<P>(i)];
     LdsRows<T, LD> lds{s_re, s_im, p};
-    if constexpr (P::S == 1) __syncthreads();  // twiddle table visible before the split
-    fft_pencil<P, false, 2>(v, t, lds, s_tw);
-    // split: X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W^k (Z[k] - conj Z[M-k]),  W = exp(-2 pi i/Nx)
-#pragma unroll
-    for (int i = 0; i < E; ++i) lds.st(t + TT * m_last<P>(i), v[i]);
-    __syncthreads();
-    cpx<T>* out = dst + row * M;
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int k = t + TT * m_last<P>(i);
-        const cpx<T> z = v[i];
-        cpx<T> r;
-        if (k == 0) {
-            r = {z.x + z.y, z.x - z.y};  // X[0] + i X[M]
-        } else {
-            const cpx<T> zc = conj(lds.ld(M - k));
-            const cpx<T> ev = scale(z + zc, (T)0.5);
-            const cpx<T> od = scale(mulmi(z - zc), (T)0.5);  // (Z - conj Z')/(2i)
-            r = ev + twmul<false>(s_tw, k, 2 * M, od);
-        }
-        if (active) out[k] = r;
-    }
+    x_forward_row<T, P, LD>(v, t, lds, s_tw, dst + row * M, active);
+}
+
+// Rows in descending order (EIFP_MALL_ORDER): the z inverse pass wrote the last
+// components last, and those are the ones still in the last-level cache.
+__device__ __forceinline__ long x_inv_row(long nrows, int np, int p) {
+    const long r = (long)blockIdx.x * np + p;
+    return EIFP_MALL_ORDER ? nrows - 1 - r : r;
 }
 
 // Inverse reads work, writes state.
@@ -133,37 +176,52 @@ k_x_inv(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
     const cpx<T>* src = md[blockIdx.y].work;
     cpx<T>* dst = md[blockIdx.y].state;
     const int t = threadIdx.x % TT, p = threadIdx.x / TT;
-    // rows in descending order (EIFP_MALL_ORDER): the z inverse pass wrote the last
-    // components last, and those are the ones still in the last-level cache
-    const long row = EIFP_MALL_ORDER ? nrows - 1 - ((long)blockIdx.x * NP + p) : (long)blockIdx.x * NP + p;
+    const long row = x_inv_row(nrows, NP, p);
     const bool active = row >= 0 && row < nrows;
     const cpx<T>* in = src + (active ? row : nrows - 1) * M;
     LdsRows<T, LD> lds{s_re, s_im, p};
     cpx<T> v[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = in[t + TT * m_first<P>(i)];
-#pragma unroll
-    for (int i = 0; i < E; ++i) lds.st(t + TT * m_first<P>(i), v[i]);
-    __syncthreads();
-    // merge: Z[k] = (X[k] + conj X[M-k]) + i W^-k (X[k] - conj X[M-k]); Z[0] from X[0], X[M]
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int k = t + TT * m_first<P>(i);
-        const cpx<T> x = v[i];
-        if (k == 0) {
-            v[i] = {x.x + x.y, x.x - x.y};
-        } else {
-            const cpx<T> xc = conj(lds.ld(M - k));
-            v[i] = (x + xc) + muli(twmul<true>(s_tw, k, 2 * M, x - xc));
-        }
-    }
-    __syncthreads();
-    fft_pencil<P, true, 2>(v, t, lds, s_tw);
+    x_inverse_row<T, P, LD>(v, t, lds, s_tw);
     cpx<T>* out = dst + row * M;
     if (active) {
 #pragma unroll
         for (int i = 0; i < E; ++i) out[t + TT * m_last<P>(i)] = v[i];
     }
+}
+
+// Between two steps (work != state): the x inverse of one step and the x forward of the
+// next on the same row.  Reads work (the spectrum after the z inverse), writes the
+// physical row to state and its forward x transform back to work: the arithmetic of
+// k_x_inv followed by k_x_fwd, with one read of the state fewer.  Rows in the order of
+// k_x_inv, so the z forward pass after it takes the components in ascending order.
+template <typename T, class P, int NP>
+__global__ void __launch_bounds__(P::T * NP)
+k_x_invfwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restrict__ twx) {
+    constexpr int M = P::N, E = P::E, TT = P::T, LD = rows_pitch<T>(M);
+    __shared__ T s_re[NP * LD];
+    __shared__ T s_im[NP * LD];
+    __shared__ cpx<T> s_tw[2 * M * TwParts<T>::value];
+    stage_table(s_tw, twx, 2 * M);
+    cpx<T>* work = md[blockIdx.y].work;
+    cpx<T>* state = md[blockIdx.y].state;
+    const int t = threadIdx.x % TT, p = threadIdx.x / TT;
+    const long row = x_inv_row(nrows, NP, p);
+    const bool active = row >= 0 && row < nrows;
+    const cpx<T>* in = work + (active ? row : nrows - 1) * M;
+    LdsRows<T, LD> lds{s_re, s_im, p};
+    cpx<T> v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = in[t + TT * m_first<P>(i)];
+    x_inverse_row<T, P, LD>(v, t, lds, s_tw);
+    cpx<T>* phys = state + row * M;
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) phys[t + TT * m_last<P>(i)] = v[i];
+    }
+    last_to_first<P>(v);
+    x_forward_row<T, P, LD>(v, t, lds, s_tw, work + row * M, active);
 }
 
 // ---------------------------------------------------------------------------------
@@ -326,7 +384,7 @@ __host__ __device__ constexpr int c2c_skew() {
 template <typename T, class P, int B, bool INV>
 __global__ void __launch_bounds__(P::T * B)
 k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, long cs,
-      const cpx<T>* __restrict__ tw, int fin_nparts) {
+      const cpx<T>* __restrict__ tw, int fin_nparts, int comp_desc) {
     constexpr int NP = P::N, E = P::E, TT = P::T;
     __shared__ double s_w[((TT * B + 63) / 64) * 2 * INV_NPART];
     const unsigned nxt = gridDim.x - (fin_nparts > 0 ? 1u : 0u);
@@ -348,11 +406,12 @@ k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, l
     xcd_tiles(EIFP_C2C_XCD, nxt, tx, ty);
     const int col = tx * B + c;
     const int o = ty;
-    // the forward pass takes the components in descending order (EIFP_MALL_ORDER): the x
-    // pass before it wrote the last components last, and those are still in the
-    // last-level cache; the inverse keeps ascending order (so the x inverse after it
-    // starts from the last component)
-    const int member = blockIdx.z / 6, comp = (EIFP_MALL_ORDER && !INV) ? 5 - (int)(blockIdx.z % 6) : blockIdx.z % 6;
+    // comp_desc: the components in descending order (EIFP_MALL_ORDER), for a forward
+    // pass after k_x_fwd, which wrote the last components last (they are still in the
+    // last-level cache); ascending after k_x_invfwd and for the inverse (so the x
+    // inverse after it starts from the last component)
+    const int member = blockIdx.z / 6;
+    const int comp = (EIFP_MALL_ORDER && comp_desc) ? 5 - (int)(blockIdx.z % 6) : (int)(blockIdx.z % 6);
     const bool active = col < M;
     const __amdgpu_buffer_rsrc_t r = make_rsrc(md[member].work + comp * cs, (unsigned)(cs * sizeof(cpx<T>)));
     const unsigned voff = (unsigned)(t * pstride + o * ostride + (active ? col : M - 1)) * sizeof(cpx<T>);

@@ -26,15 +26,20 @@ struct Grid3 {
     long cs() const { return (long)nz * ny * M; }  // complex elements per component
 };
 
+// x pass: X_FWD (state -> work), X_INV (work -> state), or X_INVFWD (between two steps
+// with work != state: the inverse into state and the next step's forward back into work)
+enum XKind { X_FWD = 0, X_INV = 1, X_INVFWD = 2 };
 template <typename T>
-int launch_x(bool inv, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st);
+int launch_x(int kind, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st);
 
 // single-component C2C along y or z on each member's work buffer (six components, in
 // place); fin_nparts > 0 also finalizes each member's invariant partials (that many
-// records) in one extra workgroup per member, alongside the transform
+// records) in one extra workgroup per member, alongside the transform.  comp_desc: a
+// forward pass takes the components in descending order (after X_FWD; ascending after
+// X_INVFWD)
 template <typename T>
 int launch_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const void* tw, hipStream_t st,
-               int fin_nparts = 0);
+               int fin_nparts = 0, int comp_desc = 1);
 
 // fused pass along `axis` on each member's work buffer: mode Z_STEP (forward, propagate,
 // partials, inverse, store), Z_FORWARD (forward, partials only; memory untouched),

@@ -102,14 +102,16 @@ inline AxisGeom axis_geom(int axis, const Grid3& g) {
 }
 
 template <typename T, int M>
-int run_x(bool inv, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st) {
+int run_x(int kind, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st) {
     using C = XCfg<T, M>;
     const long nrows = 6L * g.nz * g.ny;
     const dim3 grid((unsigned)((nrows + C::NP - 1) / C::NP), (unsigned)nm);
     const dim3 block(C::P::T * C::NP);
     const MemberDesc<T>* d = (const MemberDesc<T>*)md;
-    if (inv)
+    if (kind == X_INV)
         hipLaunchKernelGGL((k_x_inv<T, typename C::P, C::NP>), grid, block, 0, st, d, nrows, (const cpx<T>*)twx);
+    else if (kind == X_INVFWD)
+        hipLaunchKernelGGL((k_x_invfwd<T, typename C::P, C::NP>), grid, block, 0, st, d, nrows, (const cpx<T>*)twx);
     else
         hipLaunchKernelGGL((k_x_fwd<T, typename C::P, C::NP>), grid, block, 0, st, d, nrows, (const cpx<T>*)twx);
     return check_launch();
@@ -117,7 +119,7 @@ int run_x(bool inv, const Grid3& g, const void* md, int nm, const void* twx, hip
 
 template <typename T, int N>
 int run_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const void* tw, hipStream_t st,
-            int fin_nparts) {
+            int fin_nparts, int comp_desc) {
     using C = CCfg<T, N>;
     const AxisGeom a = axis_geom(axis, g);
     const unsigned ntx = (unsigned)((g.M + C::B - 1) / C::B) + (fin_nparts > 0 ? 1u : 0u);
@@ -126,10 +128,10 @@ int run_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const vo
     const MemberDesc<T>* d = (const MemberDesc<T>*)md;
     if (inv)
         hipLaunchKernelGGL((k_c2c<T, typename C::P, C::B, true>), grid, block, 0, st, d, g.M, a.pstride, a.ostride,
-                           g.cs(), (const cpx<T>*)tw, fin_nparts);
+                           g.cs(), (const cpx<T>*)tw, fin_nparts, 0);
     else
         hipLaunchKernelGGL((k_c2c<T, typename C::P, C::B, false>), grid, block, 0, st, d, g.M, a.pstride, a.ostride,
-                           g.cs(), (const cpx<T>*)tw, fin_nparts);
+                           g.cs(), (const cpx<T>*)tw, fin_nparts, comp_desc);
     return check_launch();
 }
 
@@ -213,11 +215,11 @@ int count_fused(int axis, const Grid3& g) {
 inline int axis_len(int axis, const Grid3& g) { return axis == AXIS_Y ? g.ny : g.nz; }
 
 template <typename T>
-int launch_x(bool inv, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st) {
+int launch_x(int kind, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st) {
     switch (g.M) {
 #define EIFP_CASE(MM) \
     case MM:          \
-        return run_x<T, MM>(inv, g, md, nm, twx, st);
+        return run_x<T, MM>(kind, g, md, nm, twx, st);
         EIFP_HALF_SIZES(EIFP_CASE)
 #undef EIFP_CASE
         default:
@@ -227,11 +229,11 @@ int launch_x(bool inv, const Grid3& g, const void* md, int nm, const void* twx, 
 
 template <typename T>
 int launch_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const void* tw, hipStream_t st,
-               int fin_nparts) {
+               int fin_nparts, int comp_desc) {
     switch (axis_len(axis, g)) {
 #define EIFP_CASE(N) \
     case N:          \
-        return run_c2c<T, N>(inv, axis, g, md, nm, tw, st, fin_nparts);
+        return run_c2c<T, N>(inv, axis, g, md, nm, tw, st, fin_nparts, comp_desc);
         EIFP_AXIS_SIZES(EIFP_CASE)
 #undef EIFP_CASE
         default:
@@ -276,8 +278,8 @@ int launch_finalize(const void* md, int nm, int nparts, hipStream_t st, bool ext
 }
 
 #define EIFP_INSTANTIATE(T)                                                                                   \
-    template int launch_x<T>(bool, const Grid3&, const void*, int, const void*, hipStream_t);                 \
-    template int launch_c2c<T>(bool, int, const Grid3&, const void*, int, const void*, hipStream_t, int);     \
+    template int launch_x<T>(int, const Grid3&, const void*, int, const void*, hipStream_t);                  \
+    template int launch_c2c<T>(bool, int, const Grid3&, const void*, int, const void*, hipStream_t, int, int); \
     template int launch_fused<T>(int, int, const Grid3&, const void*, int, const void*, int, hipStream_t);    \
     template int fused_partial_count<T>(int, const Grid3&);                                                   \
     template int launch_finalize<T>(const void*, int, int, hipStream_t, bool);

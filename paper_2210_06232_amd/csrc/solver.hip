@@ -2,9 +2,11 @@
 //
 // One step (Def. 2.3 / Alg. 2 with t_end = tau) is five kernels on the solver's stream:
 //   x forward (R2C split)  ->  z forward  ->  fused y (forward, propagator, invariant
-//   partials, inverse)  ->  z inverse  ->  x inverse (C2R merge)
-// followed by a one-workgroup finalize of the invariant partials.  The state stays in
-// HBM in the ABI's own layout ([6][nz][ny][nx] reals); all transforms are in place.
+//   partials, inverse)  ->  z inverse (and the finalize of the invariant partials)  ->
+//   x inverse (C2R merge)
+// The state stays in HBM in the ABI's own layout ([6][nz][ny][nx] reals); a step's
+// transforms run in the scratch buffer, and between consecutive steps of one call the
+// x inverse and the next x forward are one kernel.
 // A solver is a batch of one member: the kernels read its buffers and scalars from a
 // four-entry device descriptor array (0: step; 1: forward-only evaluation into the
 // scratch buffer; 2: forward transform into the anchor buffer; 3: jump from the anchor).
@@ -79,7 +81,9 @@ eifp_status alloc(void** p, size_t n, long long* bytes) {
 eifp_status upload_desc(eifp_solver* s, double tau, double span) {
     const Grid3& g = s->en.g;
     const PropParams p0 = make_params(g.nx, g.ny, g.nz, s->dom, s->mu, s->eps, 0.0);
-    s->desc_host[0] = DescImage{s->state, s->state, s->partials, s->inv_dev, nullptr,
+    // steps transform in the scratch buffer (the x inverse of a step and the x forward
+    // of the next then run as one kernel)
+    s->desc_host[0] = DescImage{s->state, s->scratch, s->partials, s->inv_dev, nullptr,
                                 make_params(g.nx, g.ny, g.nz, s->dom, s->mu, s->eps, tau)};
     s->desc_host[1] = DescImage{s->state, s->scratch, s->partials, s->inv_dev, nullptr, p0};
     s->desc_host[2] = DescImage{s->state, s->anchor, s->partials, s->inv_dev, nullptr, p0};
@@ -205,10 +209,8 @@ static eifp_status step_impl(eifp_solver* s, double tau, long long nsteps, doubl
             s->events.push_back(e);
         }
     }
-    for (long long n = 0; n < nsteps; ++n) {
-        hipEvent_t* ev = pass_ms ? &s->events[(size_t)7 * n] : nullptr;
-        if ((st = s->en.passes(Z_STEP, step_desc(s), 1, s->stream, ev))) return st;
-    }
+    if ((st = s->en.steps(step_desc(s), 1, nsteps, s->stream, pass_ms ? s->events.data() : nullptr, true, true)))
+        return st;
     s->t += tau * (double)nsteps;
     s->steps += nsteps;
     s->inv_current = true;
