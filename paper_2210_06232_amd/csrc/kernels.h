@@ -196,7 +196,10 @@ k_x_inv(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
 // physical row to state and its forward x transform back to work: the arithmetic of
 // k_x_inv followed by k_x_fwd, with one read of the state fewer.  Rows in the order of
 // k_x_inv, so the z forward pass after it takes the components in ascending order.
-template <typename T, class P, int NP>
+// STREAM: the physical row is stored with the non-temporal hint; no pass before the
+// next step's combined kernel reads it, and for states larger than the last-level cache
+// this leaves the cache to the spectrum, which the z forward pass reads next.
+template <typename T, class P, int NP, bool STREAM>
 __global__ void __launch_bounds__(P::T * NP)
 k_x_invfwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restrict__ twx) {
     constexpr int M = P::N, E = P::E, TT = P::T, LD = rows_pitch<T>(M);
@@ -218,7 +221,18 @@ k_x_invfwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __res
     cpx<T>* phys = state + row * M;
     if (active) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) phys[t + TT * m_last<P>(i)] = v[i];
+        for (int i = 0; i < E; ++i) {
+            cpx<T>* d = &phys[t + TT * m_last<P>(i)];
+            if constexpr (STREAM) {
+                typedef T pair_t __attribute__((ext_vector_type(2)));
+                pair_t u;
+                u.x = v[i].x;
+                u.y = v[i].y;
+                __builtin_nontemporal_store(u, reinterpret_cast<pair_t*>(d));
+            } else {
+                *d = v[i];
+            }
+        }
     }
     last_to_first<P>(v);
     x_forward_row<T, P, LD>(v, t, lds, s_tw, work + row * M, active);
