@@ -63,11 +63,15 @@ template <typename T, int N> struct CCfg {
 #ifndef EIFP_ZMIN_THREADS
 #define EIFP_ZMIN_THREADS 128
 #endif
+// LDS budget of the fused pass's exchange buffers per workgroup
+#ifndef EIFP_ZLDS_KB
+#define EIFP_ZLDS_KB 96
+#endif
 template <typename T, int N> struct ZCfg {
     using P = Plan<N, ZE<T, N>::E>;
     static constexpr int B0 = cmin(64, cmax(EIFP_ZROW_BYTES / (2 * (int)sizeof(T)), EIFP_ZMIN_THREADS / P::T));
     static constexpr int B = pow2floor(
-        cmax(1, cmin(cmin(B0, 1024 / P::T), (96 * 1024) / (skew_rows<N, zskew<P>()>() * 4 * (int)sizeof(T) * ZLockstep<T, N>::value) -
+        cmax(1, cmin(cmin(B0, 1024 / P::T), (EIFP_ZLDS_KB * 1024) / (skew_rows<N, zskew<P>()>() * 4 * (int)sizeof(T) * ZLockstep<T, N>::value) -
                          EIFP_ZPAD)));
 };
 
