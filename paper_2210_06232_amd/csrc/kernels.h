@@ -78,6 +78,66 @@ __device__ __forceinline__ double omega(int m, int n, double nu) {
 #endif
 // twx[k] = exp(-2 pi i k / Nx), k < Nx (the length-M FFT reads every second entry).
 //
+// Register index holding position block m (position t + T m) in first- or last-stage
+// order: the inverses of m_first and m_last.
+template <class P>
+__host__ __device__ constexpr int reg_of(int m, bool last) {
+    const int R = last ? P::R[P::S - 1] : P::R[0], W = P::E / R;
+    return (m % W) * R + m / W;
+}
+
+// The value of lane l ^ 1 (DPP quad permutation 1, 0, 3, 2).
+__device__ __forceinline__ float swap_lane_pair(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+}
+
+// Store a row held as v[i] at positions t + T m(i) (m = m_last if LAST, else m_first),
+// optionally with the non-temporal hint.  With 8-byte elements and 8 threads per row a
+// store instruction would cover half of each 128-byte line of the row, and the two
+// halves would reach memory separately; instead lanes t and t ^ 1 trade one value so
+// that each lane stores two adjacent elements (16 bytes) and one instruction covers
+// blocks m and m + 1 (m even) of the row: whole lines.
+template <typename T, class P, bool LAST, bool STREAM = false>
+__device__ __forceinline__ void store_row(cpx<T>* out, const cpx<T> (&v)[P::E], int t, bool active) {
+    constexpr int E = P::E, TT = P::T;
+    typedef T quad_t __attribute__((ext_vector_type(4)));
+    typedef T pair_t __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(T) == 4 && TT == 8 && E % 2 == 0) {
+        const bool odd = t & 1;
+#pragma unroll
+        for (int m = 0; m < E; m += 2) {
+            const cpx<T> a = v[reg_of<P>(m, LAST)], b = v[reg_of<P>(m + 1, LAST)];
+            const cpx<T> send = odd ? a : b;
+            const cpx<T> recv = {swap_lane_pair(send.x), swap_lane_pair(send.y)};
+            // even lane t: elements t, t + 1 of block m; odd lane t: elements t - 1, t of block m + 1
+            const cpx<T> lo = odd ? recv : a, hi = odd ? b : recv;
+            const int pos = odd ? TT * (m + 1) + t - 1 : TT * m + t;
+            quad_t q;
+            q.x = lo.x;
+            q.y = lo.y;
+            q.z = hi.x;
+            q.w = hi.y;
+            if (active) {
+                if constexpr (STREAM) __builtin_nontemporal_store(q, reinterpret_cast<quad_t*>(out + pos));
+                else *reinterpret_cast<quad_t*>(out + pos) = q;
+            }
+        }
+    } else if (active) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            cpx<T>* d = out + t + TT * (LAST ? m_last<P>(i) : m_first<P>(i));
+            if constexpr (STREAM) {
+                pair_t u;
+                u.x = v[i].x;
+                u.y = v[i].y;
+                __builtin_nontemporal_store(u, reinterpret_cast<pair_t*>(d));
+            } else {
+                *d = v[i];
+            }
+        }
+    }
+}
+
 // Row helpers.  x_forward_row: v holds the row's M complex values (pairs of reals) at
 // positions t + T m_first(i); length-M FFT, then the split
 //   X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W^k (Z[k] - conj Z[M-k]),  W = exp(-2 pi i/Nx),
@@ -96,17 +156,16 @@ __device__ __forceinline__ void x_forward_row(cpx<T> (&v)[P::E], int t, LdsRows<
     for (int i = 0; i < E; ++i) {
         const int k = t + TT * m_last<P>(i);
         const cpx<T> z = v[i];
-        cpx<T> r;
         if (k == 0) {
-            r = {z.x + z.y, z.x - z.y};  // X[0] + i X[M]
+            v[i] = {z.x + z.y, z.x - z.y};  // X[0] + i X[M]
         } else {
             const cpx<T> zc = conj(lds.ld(M - k));
             const cpx<T> ev = scale(z + zc, (T)0.5);
             const cpx<T> od = scale(mulmi(z - zc), (T)0.5);  // (Z - conj Z')/(2i)
-            r = ev + twmul<false>(s_tw, k, 2 * M, od);
+            v[i] = ev + twmul<false>(s_tw, k, 2 * M, od);
         }
-        if (active) out[k] = r;
     }
+    store_row<T, P, true>(out, v, t, active);
 }
 
 // x_inverse_row: v holds the packed half spectrum of a row at positions t + T m_first(i);
@@ -184,11 +243,7 @@ k_x_inv(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = in[t + TT * m_first<P>(i)];
     x_inverse_row<T, P, LD>(v, t, lds, s_tw);
-    cpx<T>* out = dst + row * M;
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < E; ++i) out[t + TT * m_last<P>(i)] = v[i];
-    }
+    store_row<T, P, true>(dst + row * M, v, t, active);
 }
 
 // Between two steps (work != state): the x inverse of one step and the x forward of the
@@ -218,22 +273,7 @@ k_x_invfwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __res
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = in[t + TT * m_first<P>(i)];
     x_inverse_row<T, P, LD>(v, t, lds, s_tw);
-    cpx<T>* phys = state + row * M;
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < E; ++i) {
-            cpx<T>* d = &phys[t + TT * m_last<P>(i)];
-            if constexpr (STREAM) {
-                typedef T pair_t __attribute__((ext_vector_type(2)));
-                pair_t u;
-                u.x = v[i].x;
-                u.y = v[i].y;
-                __builtin_nontemporal_store(u, reinterpret_cast<pair_t*>(d));
-            } else {
-                *d = v[i];
-            }
-        }
-    }
+    store_row<T, P, true, STREAM>(state + row * M, v, t, active);
     last_to_first<P>(v);
     x_forward_row<T, P, LD>(v, t, lds, s_tw, work + row * M, active);
 }

@@ -152,6 +152,27 @@ def test_invariants_bitwise_deterministic():
     np.testing.assert_array_equal(runs[0][1][0], runs[1][1][0])
 
 
+# Between two steps of one call the x inverse and the next x forward run as one kernel;
+# the arithmetic is that of separate calls, so n steps in one call and n calls of one
+# step give the same bits.  (256, 256, 64) FP64 is above the state size where the
+# combined kernel stores the physical field with the non-temporal hint.
+@pytest.mark.parametrize("shape,prec", [((32, 48, 16), "fp64"), ((64, 64, 64), "fp32"), ((24, 12, 48), "fp32"),
+                                        ((256, 256, 64), "fp64")])
+def test_multi_step_call_equals_single_steps_bitwise(shape, prec):
+    m = eifp()
+    H, E = inputs.random_fields(shape, DOMAIN, workload=4, p=2.0)
+    out = []
+    for calls in ((5,), (1, 1, 1, 1, 1), (2, 3)):
+        with m.Solver(H, E, DOMAIN, 1.3, 0.8, prec) as s:
+            for n in calls:
+                s.step(0.11, n)
+            out.append((s.fields(), s.invariants()))
+    for (Hg, Eg), inv in out[1:]:
+        np.testing.assert_array_equal(Hg, out[0][0][0])
+        np.testing.assert_array_equal(Eg, out[0][0][1])
+        assert inv == out[0][1]
+
+
 def _plane_wave_sum(shape, dom, t, mu, eps, modes):
     H = np.zeros((3,) + shape[::-1])
     E = np.zeros_like(H)
