@@ -167,10 +167,12 @@ def test_multi_step_call_equals_single_steps_bitwise(shape, prec):
             for n in calls:
                 s.step(0.11, n)
             out.append((s.fields(), s.invariants()))
+    ref = {k: v for k, v in out[0][1].items() if k != "t"}
     for (Hg, Eg), inv in out[1:]:
         np.testing.assert_array_equal(Hg, out[0][0][0])
         np.testing.assert_array_equal(Eg, out[0][0][1])
-        assert inv == out[0][1]
+        assert {k: v for k, v in inv.items() if k != "t"} == ref  # the time is a host-side sum
+        assert abs(inv["t"] - out[0][1]["t"]) < 1e-12
 
 
 def _plane_wave_sum(shape, dom, t, mu, eps, modes):
