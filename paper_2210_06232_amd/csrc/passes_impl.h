@@ -41,6 +41,10 @@ template <typename T, int M> struct XCfg {
 #ifndef EIFP_CROW_BYTES
 #define EIFP_CROW_BYTES 256
 #endif
+// LDS budget of the strided pass's exchange per workgroup
+#ifndef EIFP_CLDS_KB
+#define EIFP_CLDS_KB 80
+#endif
 template <typename T, int N> struct CCfg {
     using P = Plan<N, XYE<N>::E>;
     static constexpr int B0 = cmin(64, cmax(EIFP_CROW_BYTES / (2 * (int)sizeof(T)), 256 / P::T));
@@ -48,7 +52,7 @@ template <typename T, int N> struct CCfg {
     // power of two so that tiles stay aligned to the row segments
     static constexpr int B = pow2floor(
         cmax(1, cmin(cmin(B0, 1024 / P::T),
-                     (80 * 1024) / (skew_rows<N, c2c_skew<P>()>() * 2 * (int)sizeof(T)) - EIFP_LDS_PAD)));
+                     (EIFP_CLDS_KB * 1024) / (skew_rows<N, c2c_skew<P>()>() * 2 * (int)sizeof(T)) - EIFP_LDS_PAD)));
 };
 
 // Row segment targeted by a tile of the fused pass; its double-buffered exchange takes
