@@ -83,12 +83,12 @@ def run_gpu(H, E, prec: str, steps: int, warmup: int):
     state = 6.0 * ns * tsize
     slot_bytes = {"x_fwd": 2 * state / steps, "z_fwd": 2 * state, "y_fused": 2 * state, "z_inv": 2 * state,
                   "x_inv": (3 * (steps - 1) + 2) * state / steps}
-    # the dominant kernel: the longest launch (one fused y launch per step; the x slot's
-    # launches are almost all the combined kernel)
-    dominant = max(slot_bytes, key=lambda k: per_step[k] * (steps / (steps - 1) if k == "x_inv" and steps > 1 else 1))
-    launches = 1 if dominant != "x_inv" else steps
-    avg_ms = per_step[dominant] * steps / launches
-    alg_bytes = slot_bytes[dominant] * steps / launches
+    # the dominant kernel: the longest launch.  The z, fused and x-inverse slots have one
+    # launch per step (the x-inverse slot's are the combined kernel but for the last), so
+    # their time and bytes per step are per launch.
+    dominant = max(("z_fwd", "y_fused", "z_inv", "x_inv"), key=lambda k: per_step[k])
+    avg_ms = per_step[dominant]
+    alg_bytes = slot_bytes[dominant]
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic(prec, KERNEL_NAMES[dominant])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
