@@ -64,7 +64,8 @@ typedef struct {
     double div_e_l2;      /* ||div~(eps E)||_N                               (Thm 4.6) */
 } eifp_invariant_set;
 
-/* Further conserved quantities of Thms 4.1 and 4.3 for the current state, computed on
+/* Further conserved quantities of Thms 4.1 and 4.3, and drift scales, for the current
+ * state, computed on
  * the device from the spectrum (Parseval), with the time derivatives taken from the
  * semi-discrete system (2.4): d/dt H = -(1/mu) D E, d/dt E = (1/eps) D H.  The
  * remaining ones of those theorems are identities: E5 = E6 = 0 (D_k is skew) and
@@ -76,6 +77,17 @@ typedef struct {
     double e3[3];         /* E3 = mu/2 <D_k H,D_k H>_N + eps/2 <D_k E,D_k E>_N, k = x,y,z */
     double e4[3];         /* E4 = the same on H_t, E_t                                      */
     double h2;            /* H2 = <H_t,D H_t>_N/(2 eps) + <E_t,D E_t>_N/(2 mu)       (Thm 4.3) */
+    /* Drift scales of the current state: Cauchy-Schwarz bounds of the invariants that can
+     * be near zero, to measure their drift against (|I(t) - I(0)| / scale) instead of
+     * against |I(0)|.  With Sigma' the Parseval sum over the spectrum (grid-mean
+     * normalisation, as the invariants) and b the discrete wave vector:
+     *   |H1|      <= scale_helicity   = Sigma' |b| (|H^|^2/(2 eps) + |E^|^2/(2 mu))
+     *   |M1_k|    <= scale_momentum[k] = sqrt(Sigma' |H^|^2) sqrt(Sigma' b_k^2 |E^|^2)
+     *   div_h_l2  <= scale_div_h      = mu sqrt(Sigma' |b|^2 |H^|^2)   (likewise eps, E) */
+    double scale_helicity;
+    double scale_momentum[3];
+    double scale_div_h;
+    double scale_div_e;
 } eifp_invariant_ext_set;
 
 /* Create a solver and load the initial values (Def. 2.3 step 2).

@@ -25,6 +25,8 @@
  *                    physical space                                          (Thms 4.1, 4.3, 4.4, 4.6)
  *   orc_symplectic   bilinear form <E_U,H_V>_N - <E_V,H_U>_N between two
  *                    states (the quantity behind Thm 4.5)                     (Thm 4.5)
+ *   orc_drift_scales Cauchy-Schwarz bounds of H1, M1_k and the divergence
+ *                    norms, the scales their drift is measured against       (Thms 4.3, 4.4, 4.6)
  *
  * Readings where the paper is silent or garbled (each one listed in the design notes):
  *   - Psi = 0 (the zero mode, or a mode whose only nonzero index is a Nyquist index):
@@ -552,3 +554,62 @@ double orc_symplectic(int nx, int ny, int nz, const double *HU, const double *EU
 }
 
 int orc_num_invariants(void) { return ORC_NINV; }
+
+/* Drift scales of a state: the Cauchy-Schwarz bounds of the invariants that can be near
+ * zero (H1, M1_k, the divergence norms), as plain sums over the full 3-D DFT of the six
+ * components.  Parseval with the grid mean of Sec. 3: every term is divided by N_S^2.
+ *   out[0]    sum |b| (|H^|^2/(2 eps) + |E^|^2/(2 mu))          bounds |H1|   (Thm 4.3)
+ *   out[1..3] sqrt(sum |H^|^2) sqrt(sum b_k^2 |E^|^2)           bounds |M1_k| (Thm 4.4)
+ *   out[4]    mu sqrt(sum |b|^2 |H^|^2), out[5] the same for eps, E
+ *                                                   bound the divergence norms (Thm 4.6)
+ * with b = (Omega_x, Omega_y, Omega_z) of Sec. 2.3 (Nyquist entries 0). */
+int orc_drift_scales(int nx, int ny, int nz, const double *dom, double mu, double eps,
+                     const double *H, const double *E, double *out)
+{
+    if (nx < 2 || ny < 2 || nz < 2 || nx % 2 || ny % 2 || nz % 2 || !(mu > 0) || !(eps > 0)) return 1;
+    const long ns = (long)nx * ny * nz;
+    const int nn[3] = {nx, ny, nz};
+    double *a[3] = {NULL, NULL, NULL};
+    cplx *f = (cplx *)malloc(sizeof(cplx) * 6 * (size_t)ns);
+    int rc = f ? 0 : 2;
+    for (int w = 0; w < 3 && !rc; ++w) {
+        a[w] = (double *)malloc(sizeof(double) * (size_t)nn[w]);
+        if (!a[w] || orc_wavenumbers(nn[w], dom[2 * w + 1] - dom[2 * w], a[w])) rc = 2;
+    }
+    if (!rc) {
+        for (int c = 0; c < 3; ++c)
+            for (long q = 0; q < ns; ++q) {
+                f[c * ns + q] = H[c * ns + q];
+                f[(3 + c) * ns + q] = E[c * ns + q];
+            }
+        for (int c = 0; c < 6; ++c) orc_fft3(nx, ny, nz, (double *)(f + c * ns), -1);
+        double sh = 0.0, hh = 0.0, be[3] = {0.0, 0.0, 0.0}, b2h = 0.0, b2e = 0.0;
+        const double n2 = (double)ns * (double)ns;
+        for (int l = 0; l < nz; ++l)
+            for (int k = 0; k < ny; ++k)
+                for (int j = 0; j < nx; ++j) {
+                    const long q = ((long)l * ny + k) * nx + j;
+                    const double b[3] = {a[0][j], a[1][k], a[2][l]};
+                    const double bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+                    double h2 = 0.0, e2 = 0.0;
+                    for (int c = 0; c < 3; ++c) {
+                        h2 += creal(f[c * ns + q] * conj(f[c * ns + q]));
+                        e2 += creal(f[(3 + c) * ns + q] * conj(f[(3 + c) * ns + q]));
+                    }
+                    h2 /= n2;
+                    e2 /= n2;
+                    sh += sqrt(bb) * (h2 / (2.0 * eps) + e2 / (2.0 * mu));
+                    hh += h2;
+                    for (int w = 0; w < 3; ++w) be[w] += b[w] * b[w] * e2;
+                    b2h += bb * h2;
+                    b2e += bb * e2;
+                }
+        out[0] = sh;
+        for (int w = 0; w < 3; ++w) out[1 + w] = sqrt(hh) * sqrt(be[w]);
+        out[4] = mu * sqrt(b2h);
+        out[5] = eps * sqrt(b2e);
+    }
+    free(f);
+    for (int w = 0; w < 3; ++w) free(a[w]);
+    return rc;
+}

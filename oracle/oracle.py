@@ -62,8 +62,9 @@ def _get():
                                                            dp, dp, dp]
         lib.orc_symplectic.argtypes = [ctypes.c_int] * 3 + [dp] * 4
         lib.orc_symplectic.restype = ctypes.c_double
+        lib.orc_drift_scales.argtypes = [ctypes.c_int] * 3 + [dp, ctypes.c_double, ctypes.c_double, dp, dp, dp]
         for name in ("orc_dft", "orc_fft", "orc_fft3", "orc_wavenumbers", "orc_dmatrix",
-                     "orc_deriv", "orc_step", "orc_invariants"):
+                     "orc_deriv", "orc_step", "orc_invariants", "orc_drift_scales"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -179,6 +180,21 @@ def invariants(H, E, domain, mu: float, eps: float) -> dict:
     _check(_get().orc_invariants(nx, ny, nz, _p(d), float(mu), float(eps), _p(H), _p(E), _p(out)),
            "invariants")
     return dict(zip(INV_NAMES, out.tolist()))
+
+
+DRIFT_SCALE_NAMES = ("scale_H1", "scale_M1_x", "scale_M1_y", "scale_M1_z", "scale_divH", "scale_divE")
+
+
+def drift_scales(H, E, domain, mu: float, eps: float) -> dict:
+    """Cauchy-Schwarz bounds of H1, M1_k and the divergence norms (Thms 4.3, 4.4, 4.6)."""
+    H = _f64(H)
+    E = _f64(E)
+    _, nz, ny, nx = H.shape
+    d = _dom(domain)
+    out = np.empty(len(DRIFT_SCALE_NAMES))
+    _check(_get().orc_drift_scales(nx, ny, nz, _p(d), float(mu), float(eps), _p(H), _p(E), _p(out)),
+           "drift_scales")
+    return dict(zip(DRIFT_SCALE_NAMES, out.tolist()))
 
 
 def symplectic(HU, EU, HV, EV) -> float:

@@ -57,7 +57,11 @@ struct MemberDesc {
 // invariant partial sums per workgroup (all in FP64); the extended record adds the
 // energies of the derivatives and the second helicity (Thms 4.1 and 4.3)
 enum { INV_E1 = 0, INV_H1, INV_M1X, INV_M1Y, INV_M1Z, INV_DIVH, INV_DIVE, INV_NPART = 8 };
-enum { INV_E2 = 8, INV_E3X, INV_E3Y, INV_E3Z, INV_E4X, INV_E4Y, INV_E4Z, INV_H2, INV_XPART = 16 };
+enum { INV_E2 = 8, INV_E3X, INV_E3Y, INV_E3Z, INV_E4X, INV_E4Y, INV_E4Z, INV_H2 };
+// and the sums behind the drift scales (Cauchy-Schwarz bounds of H1, M1, the divergence
+// norms): sum |b| (|H|^2/(2 eps) + |E|^2/(2 mu)), sum |H|^2, sum b_k^2 |E|^2, sum |b|^2 |H|^2,
+// sum |b|^2 |E|^2 (one slot unused)
+enum { INV_SH1 = 16, INV_HH, INV_BEX, INV_BEY, INV_BEZ, INV_B2H, INV_B2E, INV_XPART = 24 };
 
 // Omega_w[m] of Sec. 2.3: nu m for m < n/2, 0 at the Nyquist index, nu (m - n) above.
 __device__ __forceinline__ double omega(int m, int n, double nu) {
@@ -543,6 +547,12 @@ __device__ __forceinline__ void accumulate_invariants(double (&acc)[Q], double w
             acc[INV_E4X + k] += w * bk2[k] * en2;
         }
         acc[INV_H2] += w * b2 * pp.inv_mu * pp.inv_eps * (hc * pp.inv_eps + ec * pp.inv_mu);
+        acc[INV_SH1] += w * sqrt(b2) * 0.5 * (h2 * pp.inv_eps + e2 * pp.inv_mu);
+        acc[INV_HH] += w * h2;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[INV_BEX + k] += w * bk2[k] * e2;
+        acc[INV_B2H] += w * b2 * h2;
+        acc[INV_B2E] += w * b2 * e2;
     }
 }
 

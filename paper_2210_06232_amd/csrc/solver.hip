@@ -303,6 +303,10 @@ eifp_status eifp_invariants_ext(eifp_solver* s, eifp_invariant_ext_set* out) {
         out->e4[k] = v[INV_E4X + k];
     }
     out->h2 = v[INV_H2];
+    out->scale_helicity = v[INV_SH1];
+    for (int k = 0; k < 3; ++k) out->scale_momentum[k] = std::sqrt(v[INV_HH]) * std::sqrt(v[INV_BEX + k]);
+    out->scale_div_h = s->mu * std::sqrt(v[INV_B2H]);
+    out->scale_div_e = s->eps * std::sqrt(v[INV_B2E]);
     for (int q = INV_NPART; q < INV_XPART; ++q)
         if (!std::isfinite(v[q])) return fail(EIFP_ERR_NONFINITE, "extended invariant %d is not finite", q);
     return EIFP_OK;

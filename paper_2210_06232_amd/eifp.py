@@ -103,6 +103,10 @@ class eifp_invariant_ext_set(ctypes.Structure):
         ("e3", ctypes.c_double * 3),
         ("e4", ctypes.c_double * 3),
         ("h2", ctypes.c_double),
+        ("scale_helicity", ctypes.c_double),
+        ("scale_momentum", ctypes.c_double * 3),
+        ("scale_div_h", ctypes.c_double),
+        ("scale_div_e", ctypes.c_double),
     ]
 
 
@@ -246,7 +250,9 @@ def eifp_invariants(handle) -> dict:
 def eifp_invariants_ext(handle) -> dict:
     x = eifp_invariant_ext_set()
     _check(load().eifp_invariants_ext(handle, ctypes.byref(x)), "eifp_invariants_ext")
-    return {"t": x.t, "steps_done": x.steps_done, "E2": x.e2, "E3": list(x.e3), "E4": list(x.e4), "H2": x.h2}
+    return {"t": x.t, "steps_done": x.steps_done, "E2": x.e2, "E3": list(x.e3), "E4": list(x.e4), "H2": x.h2,
+            "scale_helicity": x.scale_helicity, "scale_momentum": list(x.scale_momentum),
+            "scale_div_h": x.scale_div_h, "scale_div_e": x.scale_div_e}
 
 
 def eifp_fields(handle, shape):

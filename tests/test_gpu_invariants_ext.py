@@ -1,5 +1,7 @@
 """Extended invariants of Thms 4.1 and 4.3 (E2, E3_k, E4_k, H2) from the GPU's spectral
-sums against the oracle's physical-space evaluation, and their conservation."""
+sums against the oracle's physical-space evaluation, and their conservation; the drift
+scales (Cauchy-Schwarz bounds of H1, M1_k and the divergence norms) against the
+oracle's sums over the full DFT."""
 import math
 
 import numpy as np
@@ -17,6 +19,19 @@ def eifp():
     from paper_2210_06232_amd import eifp as m
     m.load()
     return m
+
+
+def compare_scales(ext, ref, tol):
+    # every scale is a sum of non-negative terms (or a product of square roots of such
+    # sums): relative tolerance.  A direction that carries nothing has a momentum scale
+    # of 0 on the GPU and the square root of the oracle's FFT round-off (~1e-15 of the
+    # largest scale) in the oracle, hence the absolute floor.
+    mmax = max(ref[f"scale_M1_{k}"] for k in "xyz")
+    assert abs(ext["scale_helicity"] - ref["scale_H1"]) <= tol * ref["scale_H1"]
+    for i, k in enumerate("xyz"):
+        assert abs(ext["scale_momentum"][i] - ref[f"scale_M1_{k}"]) <= tol * ref[f"scale_M1_{k}"] + 1e-13 * mmax
+    assert abs(ext["scale_div_h"] - ref["scale_divH"]) <= tol * ref["scale_divH"]
+    assert abs(ext["scale_div_e"] - ref["scale_divE"]) <= tol * ref["scale_divE"]
 
 
 def compare(ext, ref, tol):
@@ -46,6 +61,13 @@ def test_extended_invariants_match_oracle_fp64(shape, kind):
     ref = orc.invariants(H, E, DOMAIN, mu, eps)
     compare(ext, ref, 1e-12)
     assert abs(basic["energy"] - ref["E1"]) <= 1e-12 * ref["E1"]
+    compare_scales(ext, orc.drift_scales(H, E, DOMAIN, mu, eps), 1e-12)
+    # the scales bound the basic invariants
+    assert abs(basic["helicity"]) <= ext["scale_helicity"] * (1 + 1e-12)
+    for k in range(3):
+        assert abs(basic["momentum"][k]) <= ext["scale_momentum"][k] * (1 + 1e-12) + 1e-300
+    assert basic["div_h_l2"] <= ext["scale_div_h"] * (1 + 1e-12)
+    assert basic["div_e_l2"] <= ext["scale_div_e"] * (1 + 1e-12)
 
 
 def test_extended_invariants_conserved_and_fp32():
@@ -60,7 +82,11 @@ def test_extended_invariants_conserved_and_fp32():
         e1 = s.invariants_ext()
     compare(e1, ref, 1e-12)  # conserved: the state after 50 steps has the initial values
     assert e1["steps_done"] == 50 and e0["steps_done"] == 0
+    # the helicity scale is conserved too (per mode it is the energy over mu eps)
+    assert abs(e1["scale_helicity"] - e0["scale_helicity"]) <= 1e-12 * e0["scale_helicity"]
     with m.Solver(H, E, DOMAIN, mu, eps, "fp32") as s:
         s.step(0.07, 5)
         e32 = s.invariants_ext()
     compare(e32, ref, 1e-5)
+    with m.Solver(H, E, DOMAIN, mu, eps, "fp32") as s:
+        compare_scales(s.invariants_ext(), orc.drift_scales(H, E, DOMAIN, mu, eps), 1e-5)

@@ -148,3 +148,62 @@ def test_paper_energy_and_divergence_tables(example):
         for k in ("E1", "E2", "E3_x", "E4_x"):
             assert abs(b[k] - a[k]) / abs(a[k]) <= bound_e, (n, t_end, k)
         assert b["divH_linf"] <= bound_d and b["divE_linf"] <= bound_d
+
+
+# ---- drift scales: Cauchy-Schwarz bounds of H1, M1_k and the divergence norms --------
+
+def test_drift_scales_equality_cases():
+    n = 8
+    X, Y, Z = inputs.grid((n, n, n), CUBE)
+    mu, eps = 1.7, 0.6
+    zero = np.zeros((3, n, n, n))
+    # circularly polarised H = (cos z, sin z, 0): Re H^ and Im H^ orthogonal, equal, and
+    # their cross product along b, so |H1| reaches its bound 1/(2 eps)
+    H = np.stack([np.cos(Z), np.sin(Z), np.zeros_like(Z)])
+    sc = orc.drift_scales(H, zero, CUBE, mu, eps)
+    inv = orc.invariants(H, zero, CUBE, mu, eps)
+    assert abs(sc["scale_H1"] - 1 / (2 * eps)) < 1e-14
+    assert abs(abs(inv["H1"]) - sc["scale_H1"]) < 1e-14
+    # a gradient field (H^ parallel to b in every mode) reaches the divergence bound
+    ph = X + 2 * Y
+    H = np.stack([-np.sin(ph), -2 * np.sin(ph), 3 * np.cos(3 * Z)])
+    sc = orc.drift_scales(H, H, CUBE, mu, eps)
+    inv = orc.invariants(H, H, CUBE, mu, eps)
+    assert abs(inv["divH_l2"] - sc["scale_divH"]) < 1e-12 * sc["scale_divH"]
+    assert abs(inv["divE_l2"] - sc["scale_divE"]) < 1e-12 * sc["scale_divE"]
+    # H = h cos x, E = e sin x with e parallel to h: |M1_x| = |h||e|/2 is its bound
+    h = np.array([0.0, 1.0, 2.0])
+    H = h[:, None, None, None] * np.cos(X)[None]
+    E = 1.5 * H / np.cos(X)[None] * np.sin(X)[None]
+    sc = orc.drift_scales(H, E, CUBE, mu, eps)
+    inv = orc.invariants(H, E, CUBE, mu, eps)
+    assert abs(sc["scale_M1_x"] - 1.5 * (h @ h) / 2) < 1e-13
+    assert abs(abs(inv["M1_x"]) - sc["scale_M1_x"]) < 1e-13
+    assert sc["scale_M1_y"] < 1e-14 and sc["scale_M1_z"] < 1e-14  # no E content along y or z
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_drift_scales_bound_the_invariants(seed):
+    box = (0.0, 2 * math.pi, -1.0, 3.0, 0.5, 2.5)
+    H, E = inputs.white_noise_fields((8, 6, 10), seed)
+    mu, eps = 1.3, 0.7
+    sc = orc.drift_scales(H, E, box, mu, eps)
+    inv = orc.invariants(H, E, box, mu, eps)
+    assert abs(inv["H1"]) <= sc["scale_H1"]
+    for k in "xyz":
+        assert abs(inv[f"M1_{k}"]) <= sc[f"scale_M1_{k}"]
+    assert inv["divH_l2"] <= sc["scale_divH"] and inv["divE_l2"] <= sc["scale_divE"]
+    # a bound, not a loose one: each is within a modest factor on white noise
+    assert sc["scale_divH"] < 10 * inv["divH_l2"]
+
+
+def test_helicity_scale_conserved_by_the_scheme():
+    # per mode, |H^|^2/(2 eps) + |E^|^2/(2 mu) is the mode's energy over mu eps, which the
+    # exact flow keeps; so the helicity scale is conserved like E1
+    box = (0.0, 2 * math.pi, -1.0, 3.0, 0.5, 2.5)
+    H, E = inputs.white_noise_fields((8, 6, 10), 3)
+    mu, eps = 1.3, 0.7
+    s0 = orc.drift_scales(H, E, box, mu, eps)["scale_H1"]
+    H1, E1, _ = orc.step(H, E, box, mu, eps, 0.37, 5)
+    s1 = orc.drift_scales(H1, E1, box, mu, eps)["scale_H1"]
+    assert abs(s1 - s0) < 1e-13 * s0
