@@ -96,15 +96,50 @@ def run_gpu(H, E, prec: str, steps: int, warmup: int):
                 "kernel": KERNEL_NAMES[dominant], "pass": dominant,
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(avg_ms, 5)}
     step_bytes = sum(slot_bytes.values())
+    value = ns / (ms_per_step * 1e-3)
     return {
-        "value": ns / (ms_per_step * 1e-3),
+        "value": value,
         "ms_per_step": ms_per_step,
         "pass_ms_per_step": {k: round(v, 5) for k, v in per_step.items()},
         "roofline": roofline,
         "step_alg_bytes": step_bytes,
         "step_hbm_gbs": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+        # the method's irreducible traffic: read and write the six fields once per step
+        "method_alg_frac": round(value * 12 * tsize / (PEAK_HBM_GBS * 1e9), 4),
         "energy": inv["energy"],
     }
+
+
+def copy_ceiling(nbytes: int, reps: int = 5):
+    """Attainable HBM bandwidth on this GPU: a plain device-to-device copy of nbytes
+    (read + write counted), timed with events, best of reps."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    best = None
+    for _ in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del x, y
+    return {"bytes": nbytes, "gbs": round(2 * nbytes / (best * 1e-3) / 1e9, 1)}
+
+
+def host_cpu():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
 
 
 def cpu_baseline(H, E):
@@ -116,7 +151,7 @@ def cpu_baseline(H, E):
     dt = time.perf_counter() - t0
     return {"value": nx * ny * nz / dt, "unit": "field-point-steps/s", "cores": 1, "kind": "oracle",
             "sample": "1 step of the 256^3 workload (full grid), FP64, single thread",
-            "seconds": round(dt, 2)}
+            "seconds": round(dt, 2), "host": host_cpu()}
 
 
 def serving(n_requests: int):
@@ -126,7 +161,8 @@ def serving(n_requests: int):
         print(f"[bench] serving {msg}", file=sys.stderr, flush=True)
 
     lat = sv.run_stream(n_requests, load=0.8, pool=1, modes=("batched", "serial_fp64"), progress=note)
-    thr = sv.run_stream(n_requests, pool=1, modes=("batched", "serial_fp64", "anchored"), burst=True, progress=note)
+    thr = sv.run_stream(n_requests, pool=1, modes=("batched", "serial_own", "serial_fp64", "anchored"), burst=True,
+                        progress=note)
 
     def pick(r):
         keys = ("p50_s", "p99_s", "slowdown_p50", "slowdown_p99", "point_steps_per_s", "wall_s", "completed",
@@ -138,9 +174,14 @@ def serving(n_requests: int):
                   "[10,5000], cadence U{10..500}, budget 24 GB, max batch 32",
         "latency_load0.8": {"rate_per_s": round(lat["rate_per_s"], 4), "batched": pick(lat["batched"]),
                             "serial_fp64": pick(lat["serial_fp64"])},
-        "throughput_burst": {"batched": pick(thr["batched"]), "serial_fp64": pick(thr["serial_fp64"]),
+        # serial solves in each request's own precision separate the batching gain from
+        # the precision gain
+        "throughput_burst": {"batched": pick(thr["batched"]), "serial_own": pick(thr["serial_own"]),
+                             "serial_fp64": pick(thr["serial_fp64"]),
                              "speedup_vs_serial_fp64": round(thr["batched"]["point_steps_per_s"]
-                                                             / thr["serial_fp64"]["point_steps_per_s"], 3)},
+                                                             / thr["serial_fp64"]["point_steps_per_s"], 3),
+                             "speedup_vs_serial_own": round(thr["batched"]["point_steps_per_s"]
+                                                            / thr["serial_own"]["point_steps_per_s"], 3)},
         # outputs computed by jumps from each request's stored initial spectrum (the
         # scheme's exact flow over any span): same results up to rounding, steps between
         # outputs are not executed, so its point-steps/s is not comparable to stepping
@@ -168,6 +209,9 @@ def main():
     print(f"[bench] fp64 {r64['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
     r32 = run_gpu(H, E, "fp32", args.steps, args.warmup)
     print(f"[bench] fp32 {r32['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
+    nx, ny, nz = WORKLOAD["grid"]
+    copy = copy_ceiling(6 * nx * ny * nz * 8)
+    print(f"[bench] plain copy {copy['gbs']} GB/s", file=sys.stderr, flush=True)
     serve = None
     if args.serve_requests > 0:
         serve = serving(args.serve_requests)
@@ -194,9 +238,15 @@ def main():
         "config": WORKLOAD,
         "roofline": r64["roofline"],
         "cpu_baseline": cpu,
+        # attainable bandwidth (plain copy of the FP64 state) and the method's irreducible
+        # traffic fraction (12 words per point-step) against the 8 TB/s peak
+        "copy_ceiling": copy,
+        "method_alg_frac": r64["method_alg_frac"],
+        "step_hbm_gbs": r64["step_hbm_gbs"],
         "pass_ms_per_step": r64["pass_ms_per_step"],
         "fp32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
-                 "roofline": r32["roofline"], "pass_ms_per_step": r32["pass_ms_per_step"]},
+                 "roofline": r32["roofline"], "pass_ms_per_step": r32["pass_ms_per_step"],
+                 "method_alg_frac": r32["method_alg_frac"], "step_hbm_gbs": r32["step_hbm_gbs"]},
         "serving": serve,
         "kernel_source_hash": kernel_source_hash(),
     }
