@@ -274,7 +274,9 @@ eifp_status eifp_server_create(eifp_server **out, long long hbm_budget_bytes, in
 
 /* Device bytes one request of this shape holds while admitted: its state, plus an equal
  * snapshot buffer unless EIFP_REQ_NO_SNAPSHOT, plus an equal spectrum buffer with
- * EIFP_REQ_ANCHORED.  0 for an invalid shape or precision. */
+ * EIFP_REQ_ANCHORED, plus, for a request without EIFP_REQ_ANCHORED whose state is 64 MiB
+ * or more, an equal work buffer (its batches then run the x inverse of a step and the x
+ * forward of the next as one kernel).  0 for an invalid shape or precision. */
 long long eifp_server_footprint(int nx, int ny, int nz, eifp_precision prec, int flags);
 
 /* Queue a solve; the fields are copied before returning.  *req_id receives its id.

@@ -69,10 +69,11 @@ struct Engine {
     // the kernels (or null).  want_inv = false skips the invariant partial sums and the
     // finalize (a step between output points).
     eifp_status passes(int mode, const void* md, int nm, hipStream_t st, hipEvent_t* ev, bool want_inv = true) const;
-    // nsteps steps (mode Z_STEP), 7 events per step in ev (or null).  combine_x (only
-    // with work != state for every member): the x inverse of a step and the x forward of
-    // the next run as one kernel, which reads the state once instead of twice.
-    eifp_status steps(const void* md, int nm, long long nsteps, hipStream_t st, hipEvent_t* ev, bool want_inv,
+    // nsteps steps (mode Z_STEP), 7 events per step in ev (or null); steps n >= inv_from
+    // reduce the invariants (0: every step; nsteps: none).  combine_x (only with
+    // work != state for every member): the x inverse of a step and the x forward of the
+    // next run as one kernel, which reads the state once instead of twice.
+    eifp_status steps(const void* md, int nm, long long nsteps, hipStream_t st, hipEvent_t* ev, long long inv_from,
                       bool combine_x) const;
     // unscaled forward transform of each member's state into its work buffer
     eifp_status forward_spectrum(const void* md, int nm, hipStream_t st) const;

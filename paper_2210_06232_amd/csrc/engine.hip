@@ -82,16 +82,18 @@ eifp_status run_passes(const Engine& en, int mode, const void* md, int nm, hipSt
     return EIFP_OK;
 }
 
-// nsteps steps.  With work != state, the x inverse of each step but the last and the x
-// forward of the step after it run as one kernel (X_INVFWD), and the z forward pass
-// after it takes the components in ascending order.  Events per step as in run_passes
+// nsteps steps; steps n >= inv_from reduce the invariants.  With work != state, the x
+// inverse of each step but the last and the x forward of the step after it run as one
+// kernel (X_INVFWD), and the z forward pass after it takes the components in ascending
+// order.  Events per step as in run_passes
 // (the x forward slot is empty after the first step; the x inverse slot holds the
 // combined kernel).
 template <typename T>
 eifp_status run_steps(const Engine& en, const void* md, int nm, long long nsteps, hipStream_t st, hipEvent_t* ev,
-                      bool want_inv, bool combine_x) {
+                      long long inv_from, bool combine_x) {
     int rc;
     for (long long n = 0; n < nsteps; ++n) {
+        const bool want_inv = n >= inv_from;
         hipEvent_t* e = ev ? ev + 7 * n : nullptr;
         const bool first = n == 0 || !combine_x, last = n + 1 == nsteps || !combine_x;
         if (e) EIFP_HIP_TRY(hipEventRecord(e[0], st));
@@ -239,10 +241,10 @@ eifp_status Engine::forward_spectrum(const void* md, int nm, hipStream_t st) con
     return prec == EIFP_FP64 ? run_spectrum<double>(*this, md, nm, st) : run_spectrum<float>(*this, md, nm, st);
 }
 
-eifp_status Engine::steps(const void* md, int nm, long long nsteps, hipStream_t st, hipEvent_t* ev, bool want_inv,
-                          bool combine_x) const {
-    return prec == EIFP_FP64 ? run_steps<double>(*this, md, nm, nsteps, st, ev, want_inv, combine_x)
-                             : run_steps<float>(*this, md, nm, nsteps, st, ev, want_inv, combine_x);
+eifp_status Engine::steps(const void* md, int nm, long long nsteps, hipStream_t st, hipEvent_t* ev,
+                          long long inv_from, bool combine_x) const {
+    return prec == EIFP_FP64 ? run_steps<double>(*this, md, nm, nsteps, st, ev, inv_from, combine_x)
+                             : run_steps<float>(*this, md, nm, nsteps, st, ev, inv_from, combine_x);
 }
 
 eifp_status Engine::jump(const void* md, int nm, hipStream_t st, bool want_inv) const {

@@ -67,6 +67,7 @@ struct Req {
     void* state = nullptr;
     void* snap = nullptr;
     void* spec = nullptr;  // anchored spectrum (anchored requests)
+    void* work = nullptr;  // transform buffer of stepped requests with large states
     bool anchored = false;  // spec holds the spectrum of the initial state
     Group* g = nullptr;
     long long done = 0;    // steps completed and observed
@@ -117,9 +118,21 @@ long long group_bytes_of(const Key& k, int max_batch) {
            2 * ts * (k.nx + k.ny + k.nz);
 }
 
+// Stepped requests whose state is at least this large transform in a work buffer of
+// their own, so that a chunk's steps run the x inverse of one step and the x forward of
+// the next as one kernel (one read of the state fewer per step); their chunks are
+// enqueued kernel by kernel, which costs nothing next to kernels of this size.  Smaller
+// requests step in place from captured one-step graphs.
+constexpr long long kCombineBytes = 64LL << 20;
+
+bool uses_work(long long state_bytes, int flags) {
+    return !(flags & EIFP_REQ_ANCHORED) && state_bytes >= kCombineBytes;
+}
+
 long long footprint_of(int nx, int ny, int nz, int prec, int flags) {
     const long long sb = state_bytes_of(nx, ny, nz, prec);
-    return sb * (1 + ((flags & EIFP_REQ_NO_SNAPSHOT) ? 0 : 1) + ((flags & EIFP_REQ_ANCHORED) ? 1 : 0));
+    return sb * (1 + ((flags & EIFP_REQ_NO_SNAPSHOT) ? 0 : 1) + ((flags & EIFP_REQ_ANCHORED) ? 1 : 0) +
+                 (uses_work(sb, flags) ? 1 : 0));
 }
 
 double pct(std::vector<double> v, double q) {
@@ -197,13 +210,15 @@ eifp_status group_alloc(Group* g, int max_batch) {
     return EIFP_OK;
 }
 
+void req_free_buffers(eifp_server* sv, Req* r) {
+    if (!sv->dry)
+        for (void* p : {r->state, r->snap, r->spec, r->work})
+            if (p) (void)hipFree(p);
+    r->state = r->snap = r->spec = r->work = nullptr;
+}
+
 void req_free_device(eifp_server* sv, Req* r) {
-    if (!sv->dry) {
-        if (r->state) (void)hipFree(r->state);
-        if (r->snap) (void)hipFree(r->snap);
-        if (r->spec) (void)hipFree(r->spec);
-    }
-    r->state = r->snap = r->spec = nullptr;
+    req_free_buffers(sv, r);
     sv->used -= r->bytes;
     r->bytes = 0;
 }
@@ -257,13 +272,15 @@ void retire(eifp_server* sv, Req* r, bool ok) {
     if (ok && (r->rq.flags & EIFP_REQ_KEEP_RESULT)) {
         // keep the final state; the snapshot buffer goes back to the budget
         r->kept = true;
-        if (r->snap && !sv->dry) (void)hipFree(r->snap);
-        if (r->spec && !sv->dry) (void)hipFree(r->spec);
+        if (!sv->dry)
+            for (void* p : {r->snap, r->spec, r->work})
+                if (p) (void)hipFree(p);
         const long long extra = (long long)(!(r->rq.flags & EIFP_REQ_NO_SNAPSHOT)) +
-                                (long long)((r->rq.flags & EIFP_REQ_ANCHORED) != 0);
+                                (long long)((r->rq.flags & EIFP_REQ_ANCHORED) != 0) +
+                                (long long)uses_work(r->state_bytes, r->rq.flags);
         sv->used -= extra * r->state_bytes;
         r->bytes -= extra * r->state_bytes;
-        r->snap = r->spec = nullptr;
+        r->snap = r->spec = r->work = nullptr;
         r->has_snap = false;
     } else {
         req_free_device(sv, r);
@@ -311,11 +328,10 @@ eifp_status admit_one(eifp_server* sv, Req* r, Group* g) {
     if (!sv->dry) {
         if (hipMalloc(&r->state, r->state_bytes) != hipSuccess ||
             (!(r->rq.flags & EIFP_REQ_NO_SNAPSHOT) && hipMalloc(&r->snap, r->state_bytes) != hipSuccess) ||
-            ((r->rq.flags & EIFP_REQ_ANCHORED) && hipMalloc(&r->spec, r->state_bytes) != hipSuccess)) {
+            ((r->rq.flags & EIFP_REQ_ANCHORED) && hipMalloc(&r->spec, r->state_bytes) != hipSuccess) ||
+            (uses_work(r->state_bytes, r->rq.flags) && hipMalloc(&r->work, r->state_bytes) != hipSuccess)) {
             (void)hipGetLastError();
-            for (void* p : {r->state, r->snap, r->spec})
-                if (p) (void)hipFree(p);
-            r->state = r->snap = r->spec = nullptr;
+            req_free_buffers(sv, r);
             return fail(EIFP_ERR_OUT_OF_MEMORY, "request allocation failed");
         }
         const void* src = r->rq.prec == EIFP_FP64 ? (const void*)r->host64.data() : (const void*)r->host32.data();
@@ -460,7 +476,8 @@ eifp_status launch_chunk(eifp_server* sv, Group* g) {
         if (g->dirty) {
             for (int i = 0; i < nm; ++i) {
                 Req* r = g->members[i];
-                g->desc_host[i] = DescImage{r->state, r->state, g->partials + (size_t)i * g->nparts * INV_NPART,
+                g->desc_host[i] = DescImage{r->state, r->work ? r->work : r->state,
+                                            g->partials + (size_t)i * g->nparts * INV_NPART,
                                             g->inv_dev + (size_t)i * 8, nullptr, r->pp};
             }
             EIFP_HIP_TRY(hipMemcpyAsync(g->desc_dev, g->desc_host, nm * sizeof(DescImage), hipMemcpyHostToDevice, g->st));
@@ -470,7 +487,14 @@ eifp_status launch_chunk(eifp_server* sv, Group* g) {
         bool out_at_end = false;
         for (Req* r : g->members) out_at_end |= r->done + k == next_boundary(r);
         EIFP_HIP_TRY(hipEventRecord(g->ev0, g->st));
-        for (long long s = 0; s < k; ++s) {
+        const bool combine = uses_work(state_bytes_of(g->key.nx, g->key.ny, g->key.nz, g->key.prec), 0);
+        if (combine) {
+            // every member has a work buffer: the chunk's steps as one sequence, the x
+            // inverse of a step and the x forward of the next as one kernel
+            eifp_status st = g->en.steps(g->desc_dev, nm, k, g->st, nullptr, out_at_end ? k - 1 : k, true);
+            if (st) return st;
+        }
+        for (long long s = 0; s < (combine ? 0 : k); ++s) {
             const bool inv = out_at_end && s == k - 1;
             if (sv->flags & EIFP_SERVER_NO_GRAPHS) {
                 eifp_status st = g->en.passes(Z_STEP, g->desc_dev, nm, g->st, nullptr, inv);
@@ -595,13 +619,7 @@ void scheduler(eifp_server* sv) {
     // shutdown: wait for in-flight chunks, then free everything
     for (auto& kv : sv->groups)
         if (!sv->dry && kv.second->st) (void)hipStreamSynchronize(kv.second->st);
-    for (auto& kv : sv->reqs) {
-        Req* r = kv.second.get();
-        if (!sv->dry) {
-            if (r->state) (void)hipFree(r->state);
-            if (r->snap) (void)hipFree(r->snap);
-        }
-    }
+    for (auto& kv : sv->reqs) req_free_buffers(sv, kv.second.get());
     sv->reqs.clear();
     sv->pending.clear();
     for (auto& kv : sv->groups)

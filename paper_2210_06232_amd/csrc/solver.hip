@@ -209,7 +209,7 @@ static eifp_status step_impl(eifp_solver* s, double tau, long long nsteps, doubl
             s->events.push_back(e);
         }
     }
-    if ((st = s->en.steps(step_desc(s), 1, nsteps, s->stream, pass_ms ? s->events.data() : nullptr, true, true)))
+    if ((st = s->en.steps(step_desc(s), 1, nsteps, s->stream, pass_ms ? s->events.data() : nullptr, 0, true)))
         return st;
     s->t += tau * (double)nsteps;
     s->steps += nsteps;

@@ -217,3 +217,30 @@ def test_anchored_requests_match_solver_jumps_and_oracle():
         Ho, Eo, _ = orc.step(H, E, dom, mu, eps, tau * nsteps, 1)
         tol = FP64_TOL if prec == "fp64" else FP32_TOL
         assert energy_rel_error(Hg, Eg, Ho, Eo, mu, eps) <= tol, (i, prec)
+
+
+# States of 64 MiB or more get a work buffer, and their chunks run the x inverse of one
+# step and the x forward of the next as one kernel (invariants on the chunk's last step
+# only); the fields are still those of the plain solver, bit for bit, at every output.
+BIG = [
+    ((128, 128, 128), CUBE, 1.0, 1.4, 0.05, 9, 4, "fp64", 21),
+    ((128, 128, 128), CUBE, 1.0, 1.8, 0.03, 6, 0, "fp64", 22),
+    ((64, 128, 256), BOX, 1.0, 1.2, 0.04, 7, 3, "fp64", 23),
+]
+
+
+def test_large_states_step_with_the_combined_kernel_bitwise():
+    m = eifp()
+    assert m.eifp_server_footprint(128, 128, 128, "fp64") == 3 * 6 * 128 ** 3 * 8
+    out, st = run(m, BIG)
+    for i, case in enumerate(BIG):
+        Hs, Es, inv = solver_result(m, case)
+        Hg, Eg, step, evs = out[i]
+        assert step == case[5]
+        assert np.array_equal(Hg, Hs) and np.array_equal(Eg, Es), i
+        done = [e for e in evs if e["kind"] == "done"][0]
+        assert done["inv"]["energy"] == inv["energy"] and done["inv"]["helicity"] == inv["helicity"], i
+        cad = case[6]
+        want = [s for s in range(cad, case[5], cad)] if cad else []
+        assert [e["step"] for e in evs if e["kind"] == "output"] == want, i
+    assert st["completed"] == len(BIG)

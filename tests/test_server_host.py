@@ -46,6 +46,14 @@ def test_footprint():
     assert m.eifp_server_footprint(32, 32, 32, "fp32") == 2 * 6 * 32 ** 3 * 4
     assert m.eifp_server_footprint(32, 32, 32, "fp64", m.EIFP_REQ_NO_SNAPSHOT) == 6 * 32 ** 3 * 8
     assert m.eifp_server_footprint(64, 128, 256, "fp32") == 2 * 6 * 64 * 128 * 256 * 4
+    # stepped requests with a state of 64 MiB or more add a work buffer (anchored ones
+    # never step: none)
+    s128 = 6 * 128 ** 3 * 8
+    assert m.eifp_server_footprint(128, 128, 128, "fp64") == 3 * s128
+    assert m.eifp_server_footprint(128, 128, 128, "fp64", m.EIFP_REQ_NO_SNAPSHOT) == 2 * s128
+    assert m.eifp_server_footprint(128, 128, 128, "fp64", m.EIFP_REQ_ANCHORED) == 3 * s128
+    assert m.eifp_server_footprint(128, 128, 128, "fp32") == 2 * s128 // 2
+    assert m.eifp_server_footprint(256, 256, 256, "fp32") == 3 * 6 * 256 ** 3 * 4
     assert m.eifp_server_footprint(31, 32, 32, "fp64") == 0
     assert m.eifp_server_footprint(32, 32, 32, 7) == 0
 
