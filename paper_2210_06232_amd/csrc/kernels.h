@@ -961,8 +961,9 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx, long 
 #define EIFP_ZSWAVES32 3
 #endif
 template <typename T, class P> struct ZWavesS {
-    // FP32 lengths with a factor 3 hold 12 values per thread: two waves
-    static constexpr int value = sizeof(T) == 8 ? EIFP_ZSWAVES64 : (P::N % 3 == 0 ? 2 : EIFP_ZSWAVES32);
+    // 12 values per thread: one wave in FP64 (36 complex values held), two in FP32
+    static constexpr int value = sizeof(T) == 8 ? (P::E >= 12 ? 1 : EIFP_ZSWAVES64)
+                                                : (P::N % 3 == 0 ? 2 : EIFP_ZSWAVES32);
 };
 
 // swap area: [slot][thread] reals, slot-major so that consecutive threads use
@@ -1042,7 +1043,12 @@ struct SplitHalf {
             if (EIFP_FUSED_SB & 2) __builtin_amdgcn_sched_barrier(0);
         }
         if constexpr (kPencil) {
-            if (sum) ps.finish(acc, w, bx, bo, pp);
+            if (sum) {
+                double a[INV_NPART];
+                ps.finish(a, w, bx, bo, pp);
+#pragma unroll
+                for (int q = 0; q < INV_NPART; ++q) acc[q] += a[q];
+            }
         }
     }
 
@@ -1061,18 +1067,33 @@ struct SplitHalf {
     }
 };
 
-// Same launch geometry and partial records as k_fused, with 2 T B threads per block.
+// Same launch geometry, persistence and partial records as k_fused, with 2 T B threads
+// per block; persistent workgroups (ZPersistS) load the next tile's components as the
+// current tile's inverse transforms store theirs.
+#ifndef EIFP_ZSPERSIST64
+#define EIFP_ZSPERSIST64 1
+#endif
+#ifndef EIFP_ZSPERSIST32
+#define EIFP_ZSPERSIST32 0
+#endif
+template <typename T, class P> struct ZPersistS {
+    // FP64 at one wave per SIMD (12 values per thread) has the registers for it; at two
+    // waves the loop state spills
+    static constexpr bool value = sizeof(T) == 8 ? (EIFP_ZSPERSIST64 != 0 && P::E >= 12) : EIFP_ZSPERSIST32 != 0;
+};
+
 template <typename T, class P, int B, int MODE, int AXIS>
 __global__ void __launch_bounds__(2 * P::T * B, (ZWavesS<T, P>::value))
-k_fused_split(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pstride, long ostride, long cs,
+k_fused_split(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx, long pstride, long ostride, long cs,
               const cpx<T>* __restrict__ tw, int want_inv) {
-    constexpr int NZ = P::N, E = P::E, TT = P::T, NG = P::T * B, NT = 2 * NG, EH = E / 2;
+    constexpr bool PERSIST = ZPersistS<T, P>::value;
+    constexpr int E = P::E, TT = P::T, NG = P::T * B, NT = 2 * NG, EH = E / 2;
     constexpr int PLANE = zplane<P, B>();
     static_assert(NG % 64 == 0, "each group must be whole waves");
     static_assert(E % 2 == 0, "the modes are split in halves");
     static_assert(3 * E * NT <= 8 * PLANE, "the swap area fits in the exchange buffers");
     __shared__ T s_x[8 * PLANE];  // per group: two exchange buffers (re, im); also the swap area
-    __shared__ cpx<T> s_tw[NZ * TwParts<T>::value];
+    __shared__ cpx<T> s_tw[P::N * TwParts<T>::value];
     constexpr int Q = NQ<MODE>::value;
     __shared__ double s_red[(NT / 64) * Q];
     stage_table_plan<P>(s_tw, tw);  // ordered by stage (conflict-free reads)
@@ -1083,68 +1104,92 @@ k_fused_split(const MemberDesc<T>* __restrict__ md, int M, int n_outer, long pst
     const int lt = (int)threadIdx.x - g * NG;
     const int c = lt % B, t = lt / B;
     const int partner = g ? (int)threadIdx.x - NG : (int)threadIdx.x + NG;
-    int tx, ty;
-    xcd_tiles(EIFP_FUSED_XCD, gridDim.x, tx, ty);
-    const int col = tx * B + c;
-    const int o = ty;
-    const bool active = col < M;
+    const int G = (int)gridDim.x, ntiles = ntx * n_outer;
     const unsigned cbytes = (unsigned)cs * sizeof(cpx<T>);
-    const unsigned voff = (unsigned)(t * pstride + o * ostride + (active ? col : M - 1)) * sizeof(cpx<T>);
     const unsigned sstep = (unsigned)(TT * pstride) * sizeof(cpx<T>);
     LdsCols2<T, B, PLANE, zcol_pitch(B), zskew<P>()> lds{s_x + g * 4 * PLANE, c, 0};
-
-    cpx<T> v[3][E];
     cpx<T>* own = buf + 3 * g * cs;
     const cpx<T>* src = MODE == Z_JUMP ? mem.spec + 3 * g * cs : own;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) load_col<T, P>(v[q], make_rsrc(src + q * cs, cbytes), voff, sstep);
-    if (MODE != Z_JUMP) {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            int tq = t, cq = c;
-            asm volatile("" : "+v"(tq), "+v"(cq));
-            lds.c = cq;
-            fft_pencil<P, false, kStagedTw, EIFP_FUSED_CT != 0>(v[q], tq, lds, s_tw);
-            if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
-        }
-    }
+    struct Tile {
+        int col, o;
+        bool active;
+        unsigned voff;
+    };
+    auto tile = [&](int w) {
+        Tile a;
+        a.col = (w % ntx) * B + c;
+        a.o = w / ntx;
+        a.active = a.col < M;
+        a.voff = (unsigned)(t * pstride + a.o * ostride + (a.active ? a.col : M - 1)) * sizeof(cpx<T>);
+        return a;
+    };
+    using H0 = SplitHalf<T, P, MODE, AXIS, 0, NT>;
+    using H1 = SplitHalf<T, P, MODE, AXIS, 1, NT>;
 
-    const double bx = col == 0 ? 0.0 : pp.nu[0] * (double)col;  // packed column: Omega_x = 0 at 0 and Nx/2
-    const double bo = omega(o, n_outer, AXIS == 1 ? pp.nu[2] : pp.nu[1]);
-    const double w = col == 0 ? 1.0 : 2.0;
     double acc[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) acc[q] = 0.0;
-    const bool sum = want_inv && active;
-    using H0 = SplitHalf<T, P, MODE, AXIS, 0, NT>;
-    using H1 = SplitHalf<T, P, MODE, AXIS, 1, NT>;
-    cpx<T> oth[3][EH];
-    __syncthreads();  // every exchange of the forward transforms has been read
-    if (g == 0) H0::put(v, s_x);
-    else H1::put(v, s_x);
-    __syncthreads();
-    if (g == 0) H0::template modes<Q>(v, oth, s_x, partner, t, bx, bo, w, sum, pp, acc);
-    else H1::template modes<Q>(v, oth, s_x, partner, t, bx, bo, w, sum, pp, acc);
-    if (want_inv) block_reduce_store<NT, Q>(acc, mem.partials + ((long)ty * gridDim.x + tx) * Q, s_red);
-    if (MODE == Z_STEP || MODE == Z_JUMP) {
-        __syncthreads();  // the swap area has been read
-        if (g == 0) H0::put_back(oth, s_x);
-        else H1::put_back(oth, s_x);
-        __syncthreads();
-        if (g == 0) H0::get_back(v, s_x, partner);
-        else H1::get_back(v, s_x, partner);
-        __syncthreads();  // before the inverse transforms reuse the area as exchange buffers
+    int k = 0;
+    int wk = persist_tile(0, G);
+    Tile cur = tile(wk < ntiles ? wk : 0);
+    cpx<T> v[3][E];
+    if (wk < ntiles) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            if (MODE == Z_STEP) last_to_first<P>(v[q]);
-            int tq = t, cq = c;
-            asm volatile("" : "+v"(tq), "+v"(cq));
-            lds.c = cq;
-            fft_pencil<P, true, kStagedTw, EIFP_FUSED_CT != 0>(v[q], tq, lds, s_tw);
-            store_col<T, P>(v[q], make_rsrc(own + q * cs, cbytes), voff, sstep, active);
-            if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
-        }
+        for (int q = 0; q < 3; ++q) load_col<T, P>(v[q], make_rsrc(src + q * cs, cbytes), cur.voff, sstep);
     }
+    while (wk < ntiles) {  // uniform over the workgroup
+        if (MODE != Z_JUMP) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                int tq = t, cq = c;
+                asm volatile("" : "+v"(tq), "+v"(cq));
+                lds.c = cq;
+                fft_pencil<P, false, kStagedTw, EIFP_FUSED_CT != 0>(v[q], tq, lds, s_tw);
+                if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        const double bx = cur.col == 0 ? 0.0 : pp.nu[0] * (double)cur.col;  // packed column: Omega_x = 0 at 0 and Nx/2
+        const double bo = omega(cur.o, n_outer, AXIS == 1 ? pp.nu[2] : pp.nu[1]);
+        const double w = cur.col == 0 ? 1.0 : 2.0;
+        const bool sum = want_inv && cur.active;
+        cpx<T> oth[3][EH];
+        __syncthreads();  // every exchange of the forward transforms has been read
+        if (g == 0) H0::put(v, s_x);
+        else H1::put(v, s_x);
+        __syncthreads();
+        if (g == 0) H0::template modes<Q>(v, oth, s_x, partner, t, bx, bo, w, sum, pp, acc);
+        else H1::template modes<Q>(v, oth, s_x, partner, t, bx, bo, w, sum, pp, acc);
+        __syncthreads();  // the swap area has been read
+        ++k;
+        const int wn = PERSIST ? persist_tile(k, G) : ntiles;
+        const bool more = PERSIST && wn < ntiles;
+        const Tile nxt = tile(more ? wn : wk);
+        if (MODE == Z_STEP || MODE == Z_JUMP) {
+            if (g == 0) H0::put_back(oth, s_x);
+            else H1::put_back(oth, s_x);
+            __syncthreads();
+            if (g == 0) H0::get_back(v, s_x, partner);
+            else H1::get_back(v, s_x, partner);
+            __syncthreads();  // before the inverse transforms reuse the area as exchange buffers
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (MODE == Z_STEP) last_to_first<P>(v[q]);
+                int tq = t, cq = c;
+                asm volatile("" : "+v"(tq), "+v"(cq));
+                lds.c = cq;
+                fft_pencil<P, true, kStagedTw, EIFP_FUSED_CT != 0>(v[q], tq, lds, s_tw);
+                store_col<T, P>(v[q], make_rsrc(own + q * cs, cbytes), cur.voff, sstep, cur.active);
+                if (more) load_col<T, P>(v[q], make_rsrc(src + q * cs, cbytes), nxt.voff, sstep);
+                if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
+            }
+        } else if (more) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) load_col<T, P>(v[q], make_rsrc(src + q * cs, cbytes), nxt.voff, sstep);
+        }
+        wk = wn;
+        cur = nxt;
+    }
+    if (want_inv) block_reduce_store<NT, Q>(acc, mem.partials + (long)blockIdx.x * Q, s_red);
 }
 
 // FP64 <-> T conversion for upload / download of the state.

@@ -94,8 +94,23 @@ template <typename T, int N> struct ZCfg {
 #ifndef EIFP_FUSED_SPLIT
 #define EIFP_FUSED_SPLIT 1
 #endif
+// values per thread in the split form for lengths with a factor 3: 12 in FP32, and in
+// FP64 from length 192 (a thread holds three components, so FP64 affords the plan with
+// fewer stages: 192 = 12 4 4 instead of 6 2 2 2 2 2, 4% off the 192^3 pass at one wave
+// per SIMD); shorter FP64 lengths keep 6 at two waves, since their few tiles would not
+// fill the device at one wave
+#ifndef EIFP_ZSE3_64
+#define EIFP_ZSE3_64 12
+#endif
+#ifndef EIFP_ZSE3_64_FROM
+#define EIFP_ZSE3_64_FROM 192
+#endif
+template <typename T, int N> struct ZES {
+    static constexpr int E3 = sizeof(T) == 8 ? (N >= EIFP_ZSE3_64_FROM ? EIFP_ZSE3_64 : 6) : 12;
+    static constexpr int E = (N % 3 == 0) ? (N >= E3 ? E3 : N) : ZE<T, N>::E;
+};
 template <typename T, int N> struct ZCfgS {
-    using P = Plan<N, ZE<T, N>::E>;
+    using P = Plan<N, ZES<T, N>::E>;
     static constexpr int Bmin = cmax(1, 64 / P::T);
     static constexpr int B0 = cmax(Bmin, cmin(64, EIFP_ZROW_BYTES / (2 * (int)sizeof(T))));
     static constexpr int Bl = pow2floor(cmax(1, (120 * 1024) / (8 * skew_rows<N, zskew<P>()>() * (int)sizeof(T)) - EIFP_ZPAD));
@@ -170,17 +185,32 @@ int run_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const vo
 // queried once per process; without a device (host-only use) every tile gets its own
 // workgroup.  Every mode uses the step kernel's count, so the partial buffers and the
 // finalize agree on it.
+// The fused pass's configuration for length N: the split form (k_fused_split) or the
+// six-components-per-thread form (k_fused), its tile width, threads and persistence.
+template <typename T, int N, int AXIS> struct FusedSel {
+    static constexpr bool split = ZCfgS<T, N>::ok;
+    static constexpr int B = split ? ZCfgS<T, N>::B : ZCfg<T, N>::B;
+    static constexpr int threads = split ? 2 * ZCfgS<T, N>::P::T * ZCfgS<T, N>::B : ZCfg<T, N>::P::T * ZCfg<T, N>::B;
+    static constexpr bool persist =
+        split ? ZPersistS<T, typename ZCfgS<T, N>::P>::value : ZPersist<T>::value;
+    static const void* step_kernel() {
+        if constexpr (split)
+            return (const void*)k_fused_split<T, typename ZCfgS<T, N>::P, ZCfgS<T, N>::B, Z_STEP, AXIS>;
+        else
+            return (const void*)k_fused<T, typename ZCfg<T, N>::P, ZCfg<T, N>::B, Z_STEP, AXIS>;
+    }
+};
+
 template <typename T, int N, int AXIS>
 int fused_workgroups(const Grid3& g) {
-    using C = ZCfg<T, N>;
-    const int ntiles = ((g.M + C::B - 1) / C::B) * axis_geom(AXIS, g).n_outer;
-    if (!ZPersist<T>::value) return ntiles;
+    using S = FusedSel<T, N, AXIS>;
+    const int ntiles = ((g.M + S::B - 1) / S::B) * axis_geom(AXIS, g).n_outer;
+    if (!S::persist) return ntiles;
     static const int resident = [] {
         int dev = 0, cus = 0, nb = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused<T, typename C::P, C::B, Z_STEP, AXIS>,
-                                                         C::P::T * C::B, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, S::step_kernel(), S::threads, 0) != hipSuccess ||
             cus <= 0 || nb <= 0) {
             (void)hipGetLastError();  // leave no error behind for the next launch check
             return 0;
@@ -196,11 +226,12 @@ void run_fused_k(const Grid3& g, const void* md, int nm, const void* tw, int wan
     const AxisGeom a = axis_geom(AXIS, g);
     if constexpr (ZCfgS<T, N>::ok) {
         using C = ZCfgS<T, N>;
-        const dim3 grid((unsigned)((g.M + C::B - 1) / C::B), (unsigned)a.n_outer, (unsigned)nm);
+        const int ntx = (g.M + C::B - 1) / C::B;
+        const dim3 grid((unsigned)fused_workgroups<T, N, AXIS>(g), 1u, (unsigned)nm);
         const dim3 block(2 * C::P::T * C::B);
         hipLaunchKernelGGL((k_fused_split<T, typename C::P, C::B, MODE, AXIS>), grid, block, 0, st,
-                           (const MemberDesc<T>*)md, g.M, a.n_outer, a.pstride, a.ostride, g.cs(), (const cpx<T>*)tw,
-                           want_inv);
+                           (const MemberDesc<T>*)md, g.M, a.n_outer, ntx, a.pstride, a.ostride, g.cs(),
+                           (const cpx<T>*)tw, want_inv);
     } else {
         using C = ZCfg<T, N>;
         const int ntx = (g.M + C::B - 1) / C::B;
@@ -228,12 +259,7 @@ int run_fused(int mode, int axis, const Grid3& g, const void* md, int nm, const 
 
 template <typename T, int N>
 int count_fused(int axis, const Grid3& g) {
-    if constexpr (ZCfgS<T, N>::ok) {
-        constexpr int B = ZCfgS<T, N>::B;
-        return ((g.M + B - 1) / B) * axis_geom(axis, g).n_outer;
-    } else {
-        return axis == AXIS_Y ? fused_workgroups<T, N, AXIS_Y>(g) : -1;
-    }
+    return axis == AXIS_Y ? fused_workgroups<T, N, AXIS_Y>(g) : -1;
 }
 
 // axis lengths compiled for y and z
