@@ -62,7 +62,7 @@ struct Engine {
     // room for the extended record (INV_XPART doubles per workgroup)
     size_t partial_bytes() const { return (size_t)nparts * INV_XPART * sizeof(double); }
 
-    // One step (mode Z_STEP: x, z, fused y, z^-1, x^-1, finalize) or a forward-only
+    // One step (mode Z_STEP: x, z, fused y, z^-1 with the finalize, x^-1) or a forward-only
     // evaluation of the invariants (mode Z_FORWARD, or Z_FORWARD_EXT for the extended
     // record: state -> work, nothing stored back),
     // for nm members described by the device array md.  ev: 7 events recorded around

@@ -4,7 +4,8 @@
 //
 // Pass order of one step: x forward (R2C split, rows), z forward (C2C, single component),
 // fused y (forward, propagator, invariant partials, inverse; all six components),
-// z inverse, x inverse (C2R merge), invariant finalize.  The fused pass runs along y
+// z inverse (with the invariant finalize), x inverse (C2R merge); between two steps the
+// x inverse and the next x forward run as one kernel.  The fused pass runs along y
 // because its pencils are then M complex elements apart, while the strided z axis is
 // handled by the single-component pass, which can use wide tiles.
 //
@@ -53,7 +54,7 @@ int launch_fused(int mode, int axis, const Grid3& g, const void* md, int nm, con
 template <typename T>
 int fused_partial_count(int axis, const Grid3& g);
 
-// finalize each member's partials into its invariant record (extended: the 16-value
+// finalize each member's partials into its invariant record (extended: the INV_XPART-value
 // record of Z_FORWARD_EXT)
 template <typename T>
 int launch_finalize(const void* md, int nm, int nparts, hipStream_t st, bool extended = false);
