@@ -269,6 +269,11 @@ typedef struct {
  *                     plus per-batch tables); requests wait until theirs fits
  *   max_batch         members per batch (1..1024)
  *   flags             EIFP_SERVER_*
+ * For tests of failure handling, the environment variable EIFP_SERVER_FAULT_CHUNK=n, if
+ * set when the server is created, makes its n-th chunk (counted over all batches from 1)
+ * fail as a device error would, before anything is enqueued: the members of that batch
+ * end with an error event (status DEVICE) and their memory is returned; other requests
+ * are not affected.
  * Errors: INVALID_ARG, DEVICE (stream or thread creation failed). */
 eifp_status eifp_server_create(eifp_server **out, long long hbm_budget_bytes, int max_batch, int flags);
 

@@ -17,6 +17,8 @@
 // request's group idle.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -169,6 +171,11 @@ struct eifp_server {
     double first_arrive = -1, last_done = 0;
     bool stop = false;
     std::thread th;
+    // host-side fault injection for tests of failure isolation: with
+    // EIFP_SERVER_FAULT_CHUNK=n in the environment when the server is created, its n-th
+    // chunk (counted over all groups from 1) fails as a device error would, before
+    // anything is enqueued; its members end with an error event and the server goes on
+    long long fault_chunk = 0, chunk_attempts = 0;
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
@@ -600,7 +607,11 @@ void scheduler(eifp_server* sv) {
         for (auto& kv : sv->groups) {
             Group* g = kv.second.get();
             if (!g->in_flight && !g->members.empty() && g->readers == 0) {
-                const eifp_status st = g->key.anchored ? launch_jump_chunk(sv, g) : launch_chunk(sv, g);
+                eifp_status st;
+                if (sv->fault_chunk > 0 && ++sv->chunk_attempts == sv->fault_chunk)
+                    st = fail(EIFP_ERR_DEVICE, "injected fault at chunk %lld (EIFP_SERVER_FAULT_CHUNK)", sv->fault_chunk);
+                else
+                    st = g->key.anchored ? launch_jump_chunk(sv, g) : launch_chunk(sv, g);
                 if (st) fail_group(sv, g, st);
                 progress = true;
             }
@@ -657,6 +668,7 @@ eifp_status eifp_server_create(eifp_server** out, long long hbm_budget_bytes, in
     sv->max_batch = (flags & EIFP_SERVER_SERIAL) ? 1 : max_batch;
     sv->flags = flags;
     sv->dry = (flags & EIFP_SERVER_DRY_RUN) != 0;
+    if (const char* f = std::getenv("EIFP_SERVER_FAULT_CHUNK")) sv->fault_chunk = std::atoll(f);
     if (!sv->dry && hipGetDevice(&sv->device) != hipSuccess) {
         delete sv;
         return fail(EIFP_ERR_DEVICE, "no HIP device");

@@ -175,6 +175,31 @@ def test_multi_step_call_equals_single_steps_bitwise(shape, prec):
         assert abs(inv["t"] - out[0][1]["t"]) < 1e-12
 
 
+# Checkpoint and resume: a checkpoint is the fields (and the time); resuming is a new
+# solver initialised from them.  n steps, a checkpoint and n more give the bits of 2n
+# steps: the download and upload are exact (FP64 as is; FP32 widened to FP64 and
+# rounded back to the same values).
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_checkpoint_and_resume_bitwise(prec):
+    m = eifp()
+    H, E = inputs.random_fields((24, 32, 16), DOMAIN, workload=12, p=2.0)
+    mu, eps, tau = 1.1, 0.9, 0.09
+    with m.Solver(H, E, DOMAIN, mu, eps, prec) as s:
+        s.step(tau, 14)
+        H2, E2 = s.fields()
+        inv2 = s.invariants()
+    with m.Solver(H, E, DOMAIN, mu, eps, prec) as s:
+        s.step(tau, 7)
+        Hc, Ec = s.fields()
+    with m.Solver(Hc, Ec, DOMAIN, mu, eps, prec) as s:
+        s.step(tau, 7)
+        Hr, Er = s.fields()
+        invr = s.invariants()
+    np.testing.assert_array_equal(Hr, H2)
+    np.testing.assert_array_equal(Er, E2)
+    assert invr["energy"] == inv2["energy"] and invr["helicity"] == inv2["helicity"]
+
+
 def _plane_wave_sum(shape, dom, t, mu, eps, modes):
     H = np.zeros((3,) + shape[::-1])
     E = np.zeros_like(H)

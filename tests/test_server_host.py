@@ -208,3 +208,30 @@ def test_anchored_requests_in_dry_run():
     assert [e["step"] for e in evs[a]] == [250, 500, 750, 1000]
     assert [e["step"] for e in evs[b]] == [250, 500, 750, 1000]
     assert st["completed"] == 2
+
+
+def test_injected_fault_fails_one_batch_and_the_server_goes_on(monkeypatch):
+    # EIFP_SERVER_FAULT_CHUNK makes one chunk fail like a device error (host side, no GPU
+    # involved): exactly the members of that batch end with an error event, their memory
+    # goes back to the budget, and the rest of the stream completes
+    m = eifp()
+    monkeypatch.setenv("EIFP_SERVER_FAULT_CHUNK", "3")
+    with m.Server(1 << 34, 4, m.EIFP_SERVER_DRY_RUN) as sv:
+        ids = {}
+        for i in range(6):
+            n = (8, 16)[i % 2]
+            ids[sv.submit(zeros(n), zeros(n), CUBE, nsteps=40, cadence=10, tag=i)] = i
+        evs = events_by_request(drain_events(sv))
+        st = sv.stats()
+        errors = {rid for rid, es in evs.items() if any(e["kind"] == "error" for e in es)}
+        done = {rid for rid, es in evs.items() if any(e["kind"] == "done" for e in es)}
+        assert errors and not (errors & done) and errors | done == set(ids)
+        for rid in errors:
+            err = [e for e in evs[rid] if e["kind"] == "error"]
+            assert len(err) == 1 and err[0]["status"] == m.EIFP_ERR_DEVICE
+        assert st["failed"] == len(errors) and st["completed"] == len(done)
+        assert st["running"] == 0 and st["queued"] == 0
+        # the server still serves new requests after the fault
+        later = sv.submit(zeros(8), zeros(8), CUBE, nsteps=5, cadence=0, tag=99)
+        evs2 = events_by_request(drain_events(sv))
+        assert [e["kind"] for e in evs2[later]] == ["done"]
