@@ -9,6 +9,9 @@ not fit one pass):
       python3 paper_2210_06232_amd/profiling.py run
   python3 paper_2210_06232_amd/profiling.py summarize OUT/fetch OUT/write
 
+(`run --config i [--inputs-cache DIR]` takes a named preset of workload.py instead, and
+`summarize ... OUT.json --note TEXT` writes elsewhere.)
+
 `run` does a few FP64 and FP32 steps of the headline workload, then three plain device
 copies of a known size (the copy kernel calibrates the counters: its true traffic is
 the buffer size read plus the buffer size written).  `summarize` writes
@@ -47,16 +50,25 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def run(steps: int = 3):
+def run(steps: int = 3, config=None, cache=None):
+    """A few steps of the headline workload in both precisions (or of a named preset in
+    its own precisions), then the calibration copies."""
     import torch
     from paper_2210_06232_amd import eifp
-    from paper_2210_06232_amd.workload import HEADLINE, headline_inputs
-    H, E = headline_inputs()
-    for prec in ("fp64", "fp32"):
-        with eifp.Solver(H, E, HEADLINE["domain"], HEADLINE["mu"], HEADLINE["eps"], prec) as s:
-            s.step(HEADLINE["tau"], steps)
+    from paper_2210_06232_amd import workload
+    if config is None:
+        cfg, precs = workload.HEADLINE, ("fp64", "fp32")
+        H, E = workload.headline_inputs()
+    else:
+        cfg = workload.CONFIGS[config]
+        precs = cfg["precs"]
+        H, E = workload.config_inputs(cfg, lambda m: print("[profiling]", m, flush=True), cache=cache)
+    for prec in precs:
+        with eifp.Solver(H, E, cfg["domain"], cfg["mu"], cfg["eps"], prec) as s:
+            s.step(cfg["tau"], steps)
             s.sync()
         print(f"[profiling] {prec}: {steps} steps", flush=True)
+    del H, E
     x = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
     x.fill_(1.0)
     y = torch.empty_like(x)
@@ -90,7 +102,7 @@ def _per_kernel(rows):
     return out, copies
 
 
-def summarize(fetch_dir: str, write_dir: str, out_path: str = OUT_JSON):
+def summarize(fetch_dir: str, write_dir: str, out_path: str = OUT_JSON, note=None):
     fk, fc = _per_kernel(_rows(fetch_dir, "FETCH_SIZE"))
     wk, wc = _per_kernel(_rows(write_dir, "WRITE_SIZE"))
     # the calibration copies are the largest copy dispatches
@@ -109,16 +121,31 @@ def summarize(fetch_dir: str, write_dir: str, out_path: str = OUT_JSON):
     rec = {"source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES,
            "copy_fetch_kib_raw": round(f_kib, 1), "copy_write_kib_raw": round(w_kib, 1),
            "factor_fetch": ff, "factor_write": fw, "kernels": kernels,
-           "note": "bytes per launch; one launch of a pass covers all six components of the 256^3 state"}
+           "note": note or "bytes per launch; one launch of a pass covers all six components of the 256^3 state"}
     with open(out_path, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec, indent=1))
 
 
-if __name__ == "__main__":
-    if len(sys.argv) >= 2 and sys.argv[1] == "run":
-        run(int(sys.argv[2]) if len(sys.argv) > 2 else 3)
-    elif len(sys.argv) >= 4 and sys.argv[1] == "summarize":
-        summarize(sys.argv[2], sys.argv[3])
+def main(argv):
+    import argparse
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    r = sub.add_parser("run")
+    r.add_argument("steps", type=int, nargs="?", default=3)
+    r.add_argument("--config", type=int, default=None, help="a named preset instead of the headline workload")
+    r.add_argument("--inputs-cache", default=None)
+    m = sub.add_parser("summarize")
+    m.add_argument("fetch_dir")
+    m.add_argument("write_dir")
+    m.add_argument("out", nargs="?", default=OUT_JSON)
+    m.add_argument("--note", default=None)
+    a = ap.parse_args(argv)
+    if a.cmd == "run":
+        run(a.steps, a.config, a.inputs_cache)
     else:
-        raise SystemExit(__doc__)
+        summarize(a.fetch_dir, a.write_dir, a.out, a.note)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

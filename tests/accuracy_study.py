@@ -8,6 +8,7 @@ step of n tau from the same input (the scheme is exact in time, so stepping and 
 jump agree up to rounding).
 
 Run: python tests/accuracy_study.py --steps 2000 --every 100
+     python tests/accuracy_study.py --config 1     (128^3, FP64, 1000 steps, every 100)
 It lives with the tests because it uses the oracle as its reference.
 """
 from __future__ import annotations
@@ -36,18 +37,28 @@ def rel_err(H, E, Hr, Er, mu, eps) -> float:
 
 
 def run(n: int = 64, steps: int = 2000, every: int = 100, tau: float = 0.1, mu: float = 1.0, eps: float = 1.0):
-    from oracle import oracle as orc
     H0, E0 = inputs.random_fields((n, n, n), BOX, workload=2, p=2.0)
-    solvers = {
-        "fp64_step": eifp.Solver(H0, E0, BOX, mu, eps, "fp64"),
-        "fp32_step": eifp.Solver(H0, E0, BOX, mu, eps, "fp32"),
-        "fp32_jump": eifp.Solver(H0, E0, BOX, mu, eps, "fp32"),
-    }
+    return study(H0, E0, BOX, mu, eps, tau, steps, every, ("fp64_step", "fp32_step", "fp32_jump"))
+
+
+def run_preset(i: int, steps=None):
+    """The same study on a named preset (its inputs, box, mu, eps, tau, step count and
+    output interval), FP64 stepping only."""
+    from paper_2210_06232_amd import workload
+    cfg = workload.CONFIGS[i]
+    H0, E0 = workload.config_inputs(cfg)
+    return study(H0, E0, tuple(cfg["domain"]), cfg["mu"], cfg["eps"], cfg["tau"], steps or cfg["steps"],
+                 cfg["every"], ("fp64_step",))
+
+
+def study(H0, E0, box, mu, eps, tau, steps, every, forms):
+    from oracle import oracle as orc
+    solvers = {name: eifp.Solver(H0, E0, box, mu, eps, name.split("_")[0]) for name in forms}
     inv0 = {k: s.invariants() for k, s in solvers.items()}
     rows = []
     try:
         for k in range(every, steps + 1, every):
-            Ho, Eo, _ = orc.step(H0, E0, BOX, mu, eps, tau * k, 1)
+            Ho, Eo, _ = orc.step(H0, E0, box, mu, eps, tau * k, 1)
             row = {"step": k}
             for name, s in solvers.items():
                 (s.jump if name.endswith("jump") else s.step)(tau, every)
@@ -69,8 +80,12 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--every", type=int, default=100)
+    ap.add_argument("--config", type=int, default=None, help="a named preset (its own sizes and steps)")
     a = ap.parse_args()
-    run(a.n, a.steps, a.every)
+    if a.config is not None:
+        run_preset(a.config)
+    else:
+        run(a.n, a.steps, a.every)
 
 
 if __name__ == "__main__":

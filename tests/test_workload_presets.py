@@ -32,15 +32,27 @@ def test_standing_wave_preset_starts_at_rest_in_e():
     assert H.shape == (3, 16, 16, 16) and not E.any()
     # normalised so that the discrete mean of |H|^2 is 1
     assert abs(float((H ** 2).sum()) / 16 ** 3 - 1.0) < 1e-13
+    H3, E3 = workload.config_inputs(workload.CONFIGS[0], t0=0.3)
+    assert E3.any() and not np.array_equal(H3, H)
+
+
+def test_preset_input_cache_round_trip(tmp_path):
+    cfg = dict(workload.CONFIGS[1], grid=[8, 8, 8], workload="cache-probe-8^3")
+    a = workload.config_inputs(cfg, cache=str(tmp_path))
+    assert sorted(p.name for p in tmp_path.iterdir()) == ["cache-probe-8^3_E.npy", "cache-probe-8^3_H.npy"]
+    b = workload.config_inputs(cfg, cache=str(tmp_path))
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
 @pytest.mark.gpu
 def test_standing_wave_preset_matches_exact_solution():
+    # t0 = 0 (E starts at zero) and t0 = 0.3 (both fields non-zero)
     res = workload.run_config(0)
-    run = res["runs"]["fp64"]
-    assert run["rel_error_vs_exact"] <= 1e-12
-    assert run["max_abs_drift"]["energy"] <= 1e-13
-    assert run["point_steps_per_s"] > 0
+    assert sorted(res["runs"]) == ["fp64_t0=0", "fp64_t0=0.3"]
+    for run in res["runs"].values():
+        assert run["rel_error_vs_exact"] <= 1e-12
+        assert run["max_abs_drift"]["energy"] <= 1e-13
+        assert run["point_steps_per_s"] > 0
 
 
 @pytest.mark.gpu
