@@ -275,7 +275,9 @@ __host__ __device__ constexpr int m_last(int idx) {
 // stage s for butterfly j are entries (NS - R_0) + (r - 1) NS + j mod NS: the lanes of one
 // read then take consecutive entries instead of entries a power of two apart.
 constexpr int kStagedTw = 0;
-template <class P, int s, bool INV, int TWS, bool CT = true, typename T, class Lds>
+// CT: bit s set = the twiddle products of stage s use the table's lo parts (FP32 only)
+constexpr int kCompAll = -1;
+template <class P, int s, bool INV, int TWS, int CT = kCompAll, typename T, class Lds>
 __device__ __forceinline__ void fft_stages(cpx<T> (&v)[P::E], int t, Lds& lds, const cpx<T>* __restrict__ tw) {
     constexpr int N = P::N, E = P::E, TT = P::T;
     constexpr int R = P::R[s];
@@ -289,9 +291,9 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[P::E], int t, Lds& lds, c
 #pragma unroll
             for (int r = 1; r < R; ++r) {
                 if constexpr (TWS == kStagedTw)
-                    v[u * R + r] = twmul<INV, CT>(tw, (NS - P::R[0]) + (r - 1) * NS + jm, N, v[u * R + r]);
+                    v[u * R + r] = twmul<INV, ((CT >> s) & 1) != 0>(tw, (NS - P::R[0]) + (r - 1) * NS + jm, N, v[u * R + r]);
                 else
-                    v[u * R + r] = twmul<INV, CT>(tw, (jm * r * (N / (NS * R))) * TWS, N * TWS, v[u * R + r]);
+                    v[u * R + r] = twmul<INV, ((CT >> s) & 1) != 0>(tw, (jm * r * (N / (NS * R))) * TWS, N * TWS, v[u * R + r]);
             }
         }
         Dft<R, INV, T>::run(&v[u * R]);
@@ -340,7 +342,7 @@ __device__ __forceinline__ void last_to_first(cpx<T> (&v)[P::E]) {
 // NC pencils of the same thread transformed in lockstep: every exchange moves all NC
 // through LDS behind one synchronisation (Lds::st / ld take the pencil index), so the NC
 // transforms share their barriers and give the scheduler NC independent butterflies.
-template <class P, int s, bool INV, int TWS, bool CT, int NC, typename T, class Lds>
+template <class P, int s, bool INV, int TWS, int CT, int NC, typename T, class Lds>
 __device__ __forceinline__ void fft_stages_n(cpx<T> (&v)[NC][P::E], int t, Lds& lds, const cpx<T>* __restrict__ tw) {
     constexpr int N = P::N, E = P::E, TT = P::T;
     constexpr int R = P::R[s];
@@ -356,9 +358,9 @@ __device__ __forceinline__ void fft_stages_n(cpx<T> (&v)[NC][P::E], int t, Lds& 
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
                     if constexpr (TWS == kStagedTw)
-                        v[n][u * R + r] = twmul<INV, CT>(tw, (NS - P::R[0]) + (r - 1) * NS + jm, N, v[n][u * R + r]);
+                        v[n][u * R + r] = twmul<INV, ((CT >> s) & 1) != 0>(tw, (NS - P::R[0]) + (r - 1) * NS + jm, N, v[n][u * R + r]);
                     else
-                        v[n][u * R + r] = twmul<INV, CT>(tw, (jm * r * (N / (NS * R))) * TWS, N * TWS, v[n][u * R + r]);
+                        v[n][u * R + r] = twmul<INV, ((CT >> s) & 1) != 0>(tw, (jm * r * (N / (NS * R))) * TWS, N * TWS, v[n][u * R + r]);
                 }
             }
             Dft<R, INV, T>::run(&v[n][u * R]);
@@ -389,7 +391,7 @@ __device__ __forceinline__ void fft_stages_n(cpx<T> (&v)[NC][P::E], int t, Lds& 
     }
 }
 
-template <class P, bool INV, int TWS, bool CT = true, typename T, class Lds>
+template <class P, bool INV, int TWS, int CT = kCompAll, typename T, class Lds>
 __device__ __forceinline__ void fft_pencil(cpx<T> (&v)[P::E], int t, Lds& lds, const cpx<T>* __restrict__ tw) {
     fft_stages<P, 0, INV, TWS, CT>(v, t, lds, tw);
 }

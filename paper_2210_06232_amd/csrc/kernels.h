@@ -737,13 +737,14 @@ template <typename T, int N> struct ZWaves {
     static constexpr int value = (N % 3 == 0) ? 1 : (sizeof(T) == 8 ? EIFP_ZWAVES64 : EIFP_ZWAVES32);
 };
 
-// FP32 stage twiddles of the fused pass with (1) or without (0) the compensation terms.
-// With them an FP32 run's error grows like the square root of the step count instead
-// of linearly, but the extra live registers spill and the pass takes ~60% longer; the
-// default leaves the fused pass's table products uncompensated (its bias alone is a
-// quarter of the uncompensated transform's) and compensates everything else.
+// Which FFT stages of the fused pass use the FP32 tables' compensation terms (bit s =
+// stage s; -1 = all).  Uncompensated, the first twiddled stage alone (the 64th or 48th
+// roots of unity, whose FP32 roundings are biased low in modulus) costs about a third
+// of a unit roundoff of energy per transform, so an FP32 run's energy drifts linearly
+// and its error grows linearly; compensated, the error grows like the square root of
+// the step count.  All stages cost ~6% on the FP32 fused pass, without spills.
 #ifndef EIFP_FUSED_CT
-#define EIFP_FUSED_CT 0
+#define EIFP_FUSED_CT -1
 #endif
 
 // scheduling fences of the fused pass: bit 0 between components' transforms, bit 1
@@ -854,7 +855,7 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx, long 
                 int tq = t, cq = c;
                 asm volatile("" : "+v"(tq), "+v"(cq));
                 lds.c = cq;
-                fft_stages_n<P, 0, false, kStagedTw, EIFP_FUSED_CT != 0, NC>(
+                fft_stages_n<P, 0, false, kStagedTw, EIFP_FUSED_CT, NC>(
                     reinterpret_cast<cpx<T>(&)[NC][E]>(v[q]), tq, lds, s_tw);
                 if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);  // one group's temporaries live at a time
             }
@@ -924,7 +925,7 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx, long 
                 int tq = t, cq = c;
                 asm volatile("" : "+v"(tq), "+v"(cq));
                 lds.c = cq;
-                fft_stages_n<P, 0, true, kStagedTw, EIFP_FUSED_CT != 0, NC>(
+                fft_stages_n<P, 0, true, kStagedTw, EIFP_FUSED_CT, NC>(
                     reinterpret_cast<cpx<T>(&)[NC][E]>(v[q]), tq, lds, s_tw);
 #pragma unroll
                 for (int n = 0; n < NC; ++n) {
@@ -1144,7 +1145,7 @@ k_fused_split(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx,
                 int tq = t, cq = c;
                 asm volatile("" : "+v"(tq), "+v"(cq));
                 lds.c = cq;
-                fft_pencil<P, false, kStagedTw, EIFP_FUSED_CT != 0>(v[q], tq, lds, s_tw);
+                fft_pencil<P, false, kStagedTw, EIFP_FUSED_CT>(v[q], tq, lds, s_tw);
                 if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -1177,7 +1178,7 @@ k_fused_split(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx,
                 int tq = t, cq = c;
                 asm volatile("" : "+v"(tq), "+v"(cq));
                 lds.c = cq;
-                fft_pencil<P, true, kStagedTw, EIFP_FUSED_CT != 0>(v[q], tq, lds, s_tw);
+                fft_pencil<P, true, kStagedTw, EIFP_FUSED_CT>(v[q], tq, lds, s_tw);
                 store_col<T, P>(v[q], make_rsrc(own + q * cs, cbytes), cur.voff, sstep, cur.active);
                 if (more) load_col<T, P>(v[q], make_rsrc(src + q * cs, cbytes), nxt.voff, sstep);
                 if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
