@@ -37,7 +37,8 @@ typedef enum {
     EIFP_ERR_OUT_OF_MEMORY = 3,    /* device allocation failed */
     EIFP_ERR_DEVICE = 4,           /* a HIP call or kernel launch failed */
     EIFP_ERR_NONFINITE = 5,        /* NaN/Inf in the initial fields or in the invariants */
-    EIFP_ERR_STATE = 6             /* call not valid in the solver's current state */
+    EIFP_ERR_STATE = 6,            /* call not valid in the solver's current state */
+    EIFP_ERR_CANCELLED = 7         /* server request ended by eifp_server_cancel */
 } eifp_status;
 
 typedef enum {
@@ -262,6 +263,7 @@ typedef struct {
     long long bytes_in_use, peak_bytes, budget_bytes;
     long long chunks;           /* batched chunk launches */
     double mean_batch;          /* members per chunk, averaged over chunks */
+    long long cancelled;        /* requests ended by eifp_server_cancel (not in failed) */
 } eifp_server_stat_set;
 
 /* Create a server.
@@ -306,6 +308,17 @@ eifp_status eifp_server_fields(eifp_server *sv, long long req_id, double *H, dou
 /* Free the device memory of a finished request kept with EIFP_REQ_KEEP_RESULT.
  * Errors: INVALID_ARG (unknown id), STATE (not finished or not kept). */
 eifp_status eifp_server_release(eifp_server *sv, long long req_id);
+
+/* Cancel a queued or running request.  A queued one is dropped at once; a running one
+ * leaves its batch when the chunk in flight (if any) has completed and no
+ * eifp_server_fields copy is reading it, so that no kernel or copy still uses its
+ * memory when that memory is returned.  Either way its last event is an error event with
+ * status CANCELLED (after any output events of steps already run), and the request
+ * counts in `cancelled`, not in `failed`.  Its batch companions run on unaffected.
+ * Cancelling again before that event is a no-op.
+ * Errors: INVALID_ARG (NULL server, unknown id: never submitted or already ended without
+ * a kept result), STATE (finished with a kept result: use eifp_server_release). */
+eifp_status eifp_server_cancel(eifp_server *sv, long long req_id);
 
 /* Counters and latency percentiles so far. */
 eifp_status eifp_server_stats(eifp_server *sv, eifp_server_stat_set *out);

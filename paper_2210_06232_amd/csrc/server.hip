@@ -78,6 +78,7 @@ struct Req {
     long long snap_step = 0;  // steps done when the current snapshot was taken
     bool finished = false;
     bool kept = false;
+    bool cancel = false;   // eifp_server_cancel asked; ends where no chunk or copy uses it
     int readers = 0;       // eifp_server_fields calls copying from this request
 };
 
@@ -164,6 +165,8 @@ struct eifp_server {
     std::vector<double> lat;
     long long next_id = 1;
     long long submitted = 0, admitted = 0, completed = 0, failed = 0, running = 0, peak_running = 0;
+    long long cancelled = 0;
+    long long cancel_asks = 0;  // requests asked to cancel that have not ended yet
     long long used = 0, peak = 0;
     long long chunks = 0;
     double batch_sum = 0;
@@ -257,8 +260,13 @@ void push_event(eifp_server* sv, Req* r, int kind, eifp_status st, const double*
     sv->cv_ev.notify_all();
 }
 
-// Retire a member that finished or failed: free or keep its memory, record stats.
-void retire(eifp_server* sv, Req* r, bool ok) {
+enum class End { Done, Failed, Cancelled };
+
+// Retire a member that finished, failed or was cancelled: free or keep its memory,
+// record stats.
+void retire(eifp_server* sv, Req* r, End how) {
+    const bool ok = how == End::Done;
+    if (r->cancel) sv->cancel_asks--;
     Group* g = r->g;
     if (g) {
         g->members.erase(std::remove(g->members.begin(), g->members.end(), r), g->members.end());
@@ -273,6 +281,8 @@ void retire(eifp_server* sv, Req* r, bool ok) {
         sv->lat.push_back(t - r->t_arrive);
         sv->point_steps += (double)r->rq.nx * r->rq.ny * r->rq.nz * (double)r->rq.nsteps;
         sv->last_done = t;
+    } else if (how == End::Cancelled) {
+        sv->cancelled++;
     } else {
         sv->failed++;
     }
@@ -299,9 +309,44 @@ void fail_group(eifp_server* sv, Group* g, eifp_status st) {
     std::vector<Req*> ms = g->members;
     for (Req* r : ms) {
         push_event(sv, r, EIFP_EV_ERROR, st, nullptr);
-        retire(sv, r, false);
+        retire(sv, r, End::Failed);
     }
     g->in_flight = false;
+}
+
+// End the requests asked to cancel wherever that is safe now: queued ones at once,
+// members of a batch with no chunk in flight and no field copy reading them.  Returns
+// whether any ended.
+bool reap_cancelled(eifp_server* sv) {
+    bool progress = false;
+    for (auto it = sv->pending.begin(); it != sv->pending.end();) {
+        Req* r = *it;
+        if (!r->cancel) {
+            ++it;
+            continue;
+        }
+        it = sv->pending.erase(it);
+        push_event(sv, r, EIFP_EV_ERROR, EIFP_ERR_CANCELLED, nullptr);
+        sv->cancel_asks--;
+        sv->cancelled++;
+        sv->reqs.erase(r->id);  // r is dead after this
+        progress = true;
+    }
+    for (auto& kv : sv->groups) {
+        Group* g = kv.second.get();
+        if (g->in_flight) continue;
+        const std::vector<Req*> ms = g->members;
+        for (Req* r : ms)
+            if (r->cancel && r->readers == 0) {
+                // admitted but not yet stepped: its upload (enqueued on the idle group's
+                // stream, reading the host copy) may still be running
+                if (!sv->dry && (!r->host64.empty() || !r->host32.empty())) (void)hipStreamSynchronize(g->st);
+                push_event(sv, r, EIFP_EV_ERROR, EIFP_ERR_CANCELLED, nullptr);
+                retire(sv, r, End::Cancelled);
+                progress = true;
+            }
+    }
+    return progress;
 }
 
 // ------------------------------- admission -------------------------------------------
@@ -381,6 +426,7 @@ bool admit(eifp_server* sv) {
                 r->done = 0;
                 push_event(sv, r, EIFP_EV_ERROR, st, nullptr);
                 sv->failed++;
+                if (r->cancel) sv->cancel_asks--;
                 if (r->state || r->snap || r->spec) req_free_device(sv, r);
                 sv->reqs.erase(r->id);
             }
@@ -568,7 +614,7 @@ bool poll_group(eifp_server* sv, Group* g) {
             for (int q = 0; q < 7; ++q) finite = finite && std::isfinite(inv[q]);
         if (!finite) {
             push_event(sv, r, EIFP_EV_ERROR, EIFP_ERR_NONFINITE, inv);
-            retire(sv, r, false);
+            retire(sv, r, End::Failed);
             continue;
         }
         if (r->snap && !at_end) {
@@ -576,7 +622,7 @@ bool poll_group(eifp_server* sv, Group* g) {
             r->snap_step = r->done;
         }
         push_event(sv, r, at_end ? EIFP_EV_DONE : EIFP_EV_OUTPUT, EIFP_OK, inv);
-        if (at_end) retire(sv, r, true);
+        if (at_end) retire(sv, r, End::Done);
     }
     return true;
 }
@@ -603,6 +649,7 @@ void scheduler(eifp_server* sv) {
             Group* g = kv.second.get();
             if (g->in_flight) progress |= poll_group(sv, g);
         }
+        if (sv->cancel_asks > 0) progress |= reap_cancelled(sv);
         progress |= admit(sv);
         for (auto& kv : sv->groups) {
             Group* g = kv.second.get();
@@ -621,7 +668,17 @@ void scheduler(eifp_server* sv) {
         // until a queued request is waiting for device memory
         if (!sv->pending.empty()) drop_idle_groups(sv);
         if (sv->pending.empty() && sv->running == 0) sv->cv_ev.notify_all();  // drained
-        if (progress) continue;
+        if (progress) {
+            // let host calls take the lock between iterations (a dry-run scheduler never
+            // waits on the device, so without this it could hold the lock indefinitely)
+            lk.unlock();
+            if (sv->dry)
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+            else
+                std::this_thread::yield();
+            lk.lock();
+            continue;
+        }
         if (busy)
             sv->cv_sched.wait_for(lk, std::chrono::microseconds(50));
         else
@@ -845,6 +902,22 @@ eifp_status eifp_server_release(eifp_server* sv, long long req_id) {
     return EIFP_OK;
 }
 
+eifp_status eifp_server_cancel(eifp_server* sv, long long req_id) {
+    clear_error();
+    if (!sv) return fail(EIFP_ERR_INVALID_ARG, "NULL server");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(req_id);
+    if (it == sv->reqs.end()) return fail(EIFP_ERR_INVALID_ARG, "unknown request %lld", req_id);
+    Req* r = it->second.get();
+    if (r->finished) return fail(EIFP_ERR_STATE, "request %lld has finished (kept result: release it)", req_id);
+    if (!r->cancel) {
+        r->cancel = true;
+        sv->cancel_asks++;
+    }
+    sv->cv_sched.notify_one();
+    return EIFP_OK;
+}
+
 eifp_status eifp_server_stats(eifp_server* sv, eifp_server_stat_set* out) {
     clear_error();
     if (!sv || !out) return fail(EIFP_ERR_INVALID_ARG, "NULL argument");
@@ -874,6 +947,7 @@ eifp_status eifp_server_stats(eifp_server* sv, eifp_server_stat_set* out) {
     s.budget_bytes = sv->budget;
     s.chunks = sv->chunks;
     s.mean_batch = sv->chunks ? sv->batch_sum / (double)sv->chunks : 0.0;
+    s.cancelled = sv->cancelled;
     *out = s;
     return EIFP_OK;
 }

@@ -403,6 +403,7 @@ const char* eifp_status_string(eifp_status st) {
         case EIFP_ERR_DEVICE: return "device error";
         case EIFP_ERR_NONFINITE: return "non-finite value";
         case EIFP_ERR_STATE: return "invalid solver state";
+        case EIFP_ERR_CANCELLED: return "request cancelled";
     }
     return "unknown status";
 }

@@ -23,6 +23,7 @@ EIFP_ERR_OUT_OF_MEMORY = 3
 EIFP_ERR_DEVICE = 4
 EIFP_ERR_NONFINITE = 5
 EIFP_ERR_STATE = 6
+EIFP_ERR_CANCELLED = 7
 
 EIFP_FP64 = 0
 EIFP_FP32 = 1
@@ -92,7 +93,7 @@ class eifp_server_stat_set(ctypes.Structure):
                [(n, ctypes.c_double) for n in ("p50_s", "p99_s", "mean_s", "max_s", "point_steps", "wall_s",
                                                 "point_steps_per_s")] + \
                [(n, ctypes.c_longlong) for n in ("bytes_in_use", "peak_bytes", "budget_bytes", "chunks")] + \
-               [("mean_batch", ctypes.c_double)]
+               [("mean_batch", ctypes.c_double), ("cancelled", ctypes.c_longlong)]
 
 
 class eifp_invariant_ext_set(ctypes.Structure):
@@ -140,6 +141,7 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "eifp_server_fields": (ctypes.c_int, [_VP, ctypes.c_longlong, _DP, _DP, ctypes.POINTER(ctypes.c_longlong)]),
     "eifp_server_release": (ctypes.c_int, [_VP, ctypes.c_longlong]),
+    "eifp_server_cancel": (ctypes.c_int, [_VP, ctypes.c_longlong]),
     "eifp_server_stats": (ctypes.c_int, [_VP, ctypes.POINTER(eifp_server_stat_set)]),
     "eifp_server_drain": (ctypes.c_int, [_VP, ctypes.c_int]),
     "eifp_server_destroy": (ctypes.c_int, [_VP]),
@@ -420,6 +422,10 @@ def eifp_server_release(handle, req_id):
     _check(load().eifp_server_release(handle, int(req_id)), "eifp_server_release")
 
 
+def eifp_server_cancel(handle, req_id):
+    _check(load().eifp_server_cancel(handle, int(req_id)), "eifp_server_cancel")
+
+
 def eifp_server_stats(handle) -> dict:
     s = eifp_server_stat_set()
     _check(load().eifp_server_stats(handle, ctypes.byref(s)), "eifp_server_stats")
@@ -452,6 +458,9 @@ class Server:
 
     def release(self, req_id):
         eifp_server_release(self.handle, req_id)
+
+    def cancel(self, req_id):
+        eifp_server_cancel(self.handle, req_id)
 
     def stats(self) -> dict:
         return eifp_server_stats(self.handle)

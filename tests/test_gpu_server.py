@@ -106,6 +106,38 @@ def test_alone_equals_mix_equals_solver_bitwise():
     assert st["chunks"] >= 1
 
 
+def test_cancelled_member_leaves_its_batch_companions_unchanged():
+    # an endless request shares a batch with A; cancelled after its first output, it ends
+    # with one CANCELLED error event and no done event, and A still gives the plain
+    # solver's bits
+    m = eifp()
+    endless = ((32, 32, 32), CUBE, 1.0, 1.4, 0.05, 10 ** 9, 20, "fp64", 21)
+    with m.Server(BUDGET, 8) as sv:
+        e_id = submit(sv, m, endless, 1, flags=0)
+        a_id = submit(sv, m, A, 0)
+        t0 = time.time()
+        evs = []
+        while not any(e["req_id"] == e_id and e["kind"] == "output" for e in evs):
+            assert time.time() - t0 < 30, "no output from the endless request"
+            evs += sv.poll(256, 100)
+        sv.cancel(e_id)
+        sv.drain(60000)
+        while True:
+            got = sv.poll(4096, 0)
+            if not got:
+                break
+            evs += got
+        st = sv.stats()
+        mine = [e for e in evs if e["req_id"] == e_id]
+        assert [e["kind"] for e in mine[:-1]] == ["output"] * (len(mine) - 1)
+        assert mine[-1]["kind"] == "error" and mine[-1]["status"] == m.EIFP_ERR_CANCELLED
+        assert st["cancelled"] == 1 and st["failed"] == 0 and st["completed"] == 1 and st["running"] == 0
+        H, E, step = sv.fields(a_id, A[0])
+        sv.release(a_id)
+    Hs, Es, _ = solver_result(m, A)
+    assert step == A[5] and np.array_equal(H, Hs) and np.array_equal(E, Es)
+
+
 def test_mix_matches_oracle():
     m = eifp()
     mix, _ = run(m, MIX)

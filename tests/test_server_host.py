@@ -235,3 +235,54 @@ def test_injected_fault_fails_one_batch_and_the_server_goes_on(monkeypatch):
         later = sv.submit(zeros(8), zeros(8), CUBE, nsteps=5, cadence=0, tag=99)
         evs2 = events_by_request(drain_events(sv))
         assert [e["kind"] for e in evs2[later]] == ["done"]
+
+
+def wait_for(sv, pred, timeout_s=10.0):
+    import time
+    t = time.time()
+    while time.time() - t < timeout_s:
+        st = sv.stats()
+        if pred(st):
+            return st
+        time.sleep(0.002)
+    raise AssertionError(f"server did not reach the state: {sv.stats()}")
+
+
+def test_cancel_queued_and_running_requests():
+    # two endless requests fill the budget, a third queues behind them; cancelling ends
+    # the queued one at once and the running ones at a chunk boundary, each with one
+    # CANCELLED error event, returns their memory, and later requests still run
+    m = eifp()
+    fp = m.eifp_server_footprint(32, 32, 32, "fp64")
+    with m.Server(int(2.5 * fp), 4, m.EIFP_SERVER_DRY_RUN) as sv:
+        a = sv.submit(zeros(32), zeros(32), CUBE, nsteps=10 ** 12, cadence=0, tag=1)
+        b = sv.submit(zeros(32), zeros(32), CUBE, nsteps=10 ** 12, cadence=0, tag=2)
+        wait_for(sv, lambda st: st["running"] == 2)
+        c = sv.submit(zeros(32), zeros(32), CUBE, nsteps=5, cadence=0, tag=3)
+        wait_for(sv, lambda st: st["queued"] == 1)
+        sv.cancel(c)
+        sv.cancel(c)  # again before its event: no-op
+        sv.cancel(a)
+        wait_for(sv, lambda st: st["cancelled"] == 2 and st["running"] == 1 and st["queued"] == 0)
+        d = sv.submit(zeros(32), zeros(32), CUBE, nsteps=5, cadence=0, tag=4)
+        wait_for(sv, lambda st: st["completed"] == 1)
+        sv.cancel(b)
+        evs = events_by_request(drain_events(sv))
+        st = sv.stats()
+        for rid in (a, b, c):
+            assert [e["kind"] for e in evs[rid]] == ["error"], evs[rid]
+            assert evs[rid][0]["status"] == m.EIFP_ERR_CANCELLED
+        assert evs[c][0]["step"] == 0 and evs[a][0]["step"] > 0
+        assert [e["kind"] for e in evs[d]] == ["done"]
+        assert st["cancelled"] == 3 and st["completed"] == 1 and st["failed"] == 0
+        assert st["running"] == 0 and st["queued"] == 0 and st["peak_bytes"] <= int(2.5 * fp)
+        # ended requests are unknown to cancel; a kept result is released, not cancelled
+        with pytest.raises(m.EifpError) as ei:
+            sv.cancel(a)
+        assert ei.value.status == m.EIFP_ERR_INVALID_ARG
+        k = sv.submit(zeros(8), zeros(8), CUBE, nsteps=3, cadence=0, tag=5, flags=m.EIFP_REQ_KEEP_RESULT)
+        drain_events(sv)
+        with pytest.raises(m.EifpError) as ei:
+            sv.cancel(k)
+        assert ei.value.status == m.EIFP_ERR_STATE
+        sv.release(k)
