@@ -1,0 +1,39 @@
+"""Host-side parts of bench.py that need no GPU: the one-GPU refusal and the traffic
+lookup against the committed counter summary."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+    assert not r.stdout.strip().startswith("{")
+
+
+def test_traffic_lookup_follows_the_source_hash(tmp_path, monkeypatch):
+    import bench
+    with open(os.path.join(ROOT, "profiles", "traffic_256cubed.json")) as f:
+        rec = json.load(f)
+    if rec["source_hash"] != bench.kernel_source_hash():
+        # taken on other kernel sources: the bench must not use it
+        assert bench.measured_traffic("fp64", "k_fused") is None
+        return
+    for prec, word in (("fp64", 8), ("fp32", 4)):
+        state = 6 * 256 ** 3 * word
+        for k in ("k_c2c", "k_fused", "k_x_fwd", "k_x_inv"):
+            t = bench.measured_traffic(prec, k)
+            assert t is not None and abs(t / (2 * state) - 1) < 0.05, (prec, k, t)
+        assert abs(bench.measured_traffic(prec, "k_x_invfwd") / (3 * state) - 1) < 0.05
+    # a summary stamped with other sources is ignored
+    stale = dict(rec, source_hash="0" * 16)
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic_256cubed.json").write_text(json.dumps(stale))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("fp64", "k_fused") is None
