@@ -560,9 +560,10 @@ template <> struct BufIO<double> {
         const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0);
         return __builtin_bit_cast(cpx<double>, u);
     }
+    template <int AUX = 0>
     __device__ __forceinline__ static void st(cpx<double> v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
         using U4 = __attribute__((ext_vector_type(4))) unsigned int;
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v), r, (int)vo, (int)so, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v), r, (int)vo, (int)so, AUX);
     }
 };
 template <> struct BufIO<float> {
@@ -570,9 +571,10 @@ template <> struct BufIO<float> {
         const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0);
         return __builtin_bit_cast(cpx<float>, u);
     }
+    template <int AUX = 0>
     __device__ __forceinline__ static void st(cpx<float> v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
         using U2 = __attribute__((ext_vector_type(2))) unsigned int;
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, (int)vo, (int)so, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, (int)vo, (int)so, AUX);
     }
 };
 

@@ -295,12 +295,23 @@ __device__ __forceinline__ void load_col(cpx<T> (&v)[P::E], __amdgpu_buffer_rsrc
     for (int i = 0; i < P::E; ++i) v[i] = BufIO<T>::ld(r, voff, (unsigned)m_first<P>(i) * sstep);
 }
 
-template <typename T, class P>
+// Cache policy of the column stores (the buffer store's cache-policy operand; 2 = the
+// non-temporal hint).  The z passes store non-temporally: their output streams past the
+// caches, which takes ~6% off the z inverse at 256^3 (FP64) for ~2% on the x kernel that
+// reads it next, ~1% per step in both forms.  The fused pass keeps the default (its
+// non-temporal stores cost it 6%).
+#ifndef EIFP_FUSED_ST_AUX
+#define EIFP_FUSED_ST_AUX 0
+#endif
+#ifndef EIFP_C2C_ST_AUX
+#define EIFP_C2C_ST_AUX 2
+#endif
+template <typename T, class P, int AUX = 0>
 __device__ __forceinline__ void store_col(const cpx<T> (&v)[P::E], __amdgpu_buffer_rsrc_t r, unsigned voff,
                                           unsigned sstep, bool active) {
     if (active) {
 #pragma unroll
-        for (int i = 0; i < P::E; ++i) BufIO<T>::st(v[i], r, voff, (unsigned)m_last<P>(i) * sstep);
+        for (int i = 0; i < P::E; ++i) BufIO<T>::template st<AUX>(v[i], r, voff, (unsigned)m_last<P>(i) * sstep);
     }
 }
 
@@ -478,7 +489,7 @@ k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, l
     load_col<T, P>(v, r, voff, sstep);
     LdsCols<T, B, PITCH, SK> lds{s_re, s_im, c};
     fft_pencil<P, INV, EIFP_C2C_STW ? kStagedTw : 1>(v, t, lds, s_tw);
-    store_col<T, P>(v, r, voff, sstep, active);
+    store_col<T, P, EIFP_C2C_ST_AUX>(v, r, voff, sstep, active);
 }
 
 // ---------------------------------------------------------------------------------
@@ -929,7 +940,7 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx, long 
                     reinterpret_cast<cpx<T>(&)[NC][E]>(v[q]), tq, lds, s_tw);
 #pragma unroll
                 for (int n = 0; n < NC; ++n) {
-                    store_col<T, P>(v[q + n], make_rsrc(buf + (q + n) * cs, cbytes), cur.voff, sstep, cur.active);
+                    store_col<T, P, EIFP_FUSED_ST_AUX>(v[q + n], make_rsrc(buf + (q + n) * cs, cbytes), cur.voff, sstep, cur.active);
                     if (more) load_col<T, P>(v[q + n], make_rsrc(src + (q + n) * cs, cbytes), nxt.voff, sstep);
                 }
                 if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
@@ -1179,7 +1190,7 @@ k_fused_split(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx,
                 asm volatile("" : "+v"(tq), "+v"(cq));
                 lds.c = cq;
                 fft_pencil<P, true, kStagedTw, EIFP_FUSED_CT>(v[q], tq, lds, s_tw);
-                store_col<T, P>(v[q], make_rsrc(own + q * cs, cbytes), cur.voff, sstep, cur.active);
+                store_col<T, P, EIFP_FUSED_ST_AUX>(v[q], make_rsrc(own + q * cs, cbytes), cur.voff, sstep, cur.active);
                 if (more) load_col<T, P>(v[q], make_rsrc(src + q * cs, cbytes), nxt.voff, sstep);
                 if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
             }
