@@ -296,16 +296,16 @@ __device__ __forceinline__ void load_col(cpx<T> (&v)[P::E], __amdgpu_buffer_rsrc
 }
 
 // Cache policy of the column stores (the buffer store's cache-policy operand; 2 = the
-// non-temporal hint).  The z passes store non-temporally: their output streams past the
-// caches, which takes ~6% off the z inverse at 256^3 (FP64) for ~2% on the x kernel that
-// reads it next, ~1% per step in both forms.  The fused pass keeps the default (its
-// non-temporal stores cost it 6%).
+// non-temporal hint).  The z passes store non-temporally when the state is larger than
+// the last-level cache can usefully hold (the launcher's choice, the same bound as the
+// x kernel's streaming stores): their output then streams past the caches, which takes
+// ~6% off the z inverse at 256^3 (FP64) for ~2% on the x kernel that reads it next, ~1%
+// per step in both forms.  The fused pass keeps the default (non-temporal stores cost
+// it 6%).
 #ifndef EIFP_FUSED_ST_AUX
 #define EIFP_FUSED_ST_AUX 0
 #endif
-#ifndef EIFP_C2C_ST_AUX
-#define EIFP_C2C_ST_AUX 2
-#endif
+constexpr int kStoreNT = 2;
 template <typename T, class P, int AUX = 0>
 __device__ __forceinline__ void store_col(const cpx<T> (&v)[P::E], __amdgpu_buffer_rsrc_t r, unsigned voff,
                                           unsigned sstep, bool active) {
@@ -450,7 +450,7 @@ __host__ __device__ constexpr int c2c_skew() {
     while ((1 << k) < P::R[0]) ++k;
     return k;
 }
-template <typename T, class P, int B, bool INV>
+template <typename T, class P, int B, bool INV, int ST_AUX = 0>
 __global__ void __launch_bounds__(P::T * B)
 k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, long cs,
       const cpx<T>* __restrict__ tw, int fin_nparts, int comp_desc) {
@@ -489,7 +489,7 @@ k_c2c(const MemberDesc<T>* __restrict__ md, int M, long pstride, long ostride, l
     load_col<T, P>(v, r, voff, sstep);
     LdsCols<T, B, PITCH, SK> lds{s_re, s_im, c};
     fft_pencil<P, INV, EIFP_C2C_STW ? kStagedTw : 1>(v, t, lds, s_tw);
-    store_col<T, P, EIFP_C2C_ST_AUX>(v, r, voff, sstep, active);
+    store_col<T, P, ST_AUX>(v, r, voff, sstep, active);
 }
 
 // ---------------------------------------------------------------------------------

@@ -170,9 +170,17 @@ int run_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const vo
     const dim3 grid(ntx, (unsigned)a.n_outer, (unsigned)(6 * nm));
     const dim3 block(C::P::T * C::B);
     const MemberDesc<T>* d = (const MemberDesc<T>*)md;
-    if (inv)
+    // large states: non-temporal stores (see kStoreNT)
+    const bool nt = stream_phys(g, sizeof(T));
+    if (inv && nt)
+        hipLaunchKernelGGL((k_c2c<T, typename C::P, C::B, true, kStoreNT>), grid, block, 0, st, d, g.M, a.pstride,
+                           a.ostride, g.cs(), (const cpx<T>*)tw, fin_nparts, 0);
+    else if (inv)
         hipLaunchKernelGGL((k_c2c<T, typename C::P, C::B, true>), grid, block, 0, st, d, g.M, a.pstride, a.ostride,
                            g.cs(), (const cpx<T>*)tw, fin_nparts, 0);
+    else if (nt)
+        hipLaunchKernelGGL((k_c2c<T, typename C::P, C::B, false, kStoreNT>), grid, block, 0, st, d, g.M, a.pstride,
+                           a.ostride, g.cs(), (const cpx<T>*)tw, fin_nparts, comp_desc);
     else
         hipLaunchKernelGGL((k_c2c<T, typename C::P, C::B, false>), grid, block, 0, st, d, g.M, a.pstride, a.ostride,
                            g.cs(), (const cpx<T>*)tw, fin_nparts, comp_desc);
