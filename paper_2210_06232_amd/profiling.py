@@ -9,7 +9,7 @@ not fit one pass):
       python3 paper_2210_06232_amd/profiling.py run
   python3 paper_2210_06232_amd/profiling.py summarize OUT/fetch OUT/write
 
-(`run --config i [--inputs-cache DIR]` takes a named preset of workload.py instead, and
+(`run --preset i [--inputs-cache DIR]` takes a named preset of workload.py instead, and
 `summarize ... OUT.json --note TEXT` writes elsewhere.)
 
 `run` does a few FP64 and FP32 steps of the headline workload, then three plain device
@@ -50,19 +50,19 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def run(steps: int = 3, config=None, cache=None):
+def run(steps: int = 3, preset=None, cache=None):
     """A few steps of the headline workload in both precisions (or of a named preset in
     its own precisions), then the calibration copies."""
     import torch
     from paper_2210_06232_amd import eifp
     from paper_2210_06232_amd import workload
-    if config is None:
+    if preset is None:
         cfg, precs = workload.HEADLINE, ("fp64", "fp32")
         H, E = workload.headline_inputs()
     else:
-        cfg = workload.CONFIGS[config]
+        cfg = workload.PRESETS[preset]
         precs = cfg["precs"]
-        H, E = workload.config_inputs(cfg, lambda m: print("[profiling]", m, flush=True), cache=cache)
+        H, E = workload.preset_inputs(cfg, lambda m: print("[profiling]", m, flush=True), cache=cache)
     for prec in precs:
         with eifp.Solver(H, E, cfg["domain"], cfg["mu"], cfg["eps"], prec) as s:
             s.step(cfg["tau"], steps)
@@ -133,7 +133,7 @@ def main(argv):
     sub = ap.add_subparsers(dest="cmd", required=True)
     r = sub.add_parser("run")
     r.add_argument("steps", type=int, nargs="?", default=3)
-    r.add_argument("--config", type=int, default=None, help="a named preset instead of the headline workload")
+    r.add_argument("--preset", type=int, default=None, help="a named preset instead of the headline workload")
     r.add_argument("--inputs-cache", default=None)
     m = sub.add_parser("summarize")
     m.add_argument("fetch_dir")
@@ -142,7 +142,7 @@ def main(argv):
     m.add_argument("--note", default=None)
     a = ap.parse_args(argv)
     if a.cmd == "run":
-        run(a.steps, a.config, a.inputs_cache)
+        run(a.steps, a.preset, a.inputs_cache)
     else:
         summarize(a.fetch_dir, a.write_dir, a.out, a.note)
 

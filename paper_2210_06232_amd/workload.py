@@ -27,7 +27,7 @@ def headline_inputs():
 # rate and the drift of the invariants (python -m paper_2210_06232_amd.workload)
 # ---------------------------------------------------------------------------------
 CUBE = [0.0, 2 * math.pi, 0.0, 2 * math.pi, 0.0, 2 * math.pi]
-CONFIGS = {
+PRESETS = {
     0: {"workload": "standing-wave-16^3-mu1-eps1-tau0.01", "grid": [16, 16, 16], "domain": CUBE,
         "mu": 1.0, "eps": 1.0, "tau": 0.01, "steps": 100, "every": 10, "precs": ["fp64"], "fields": "standing",
         "t0": [0.0, 0.3]},
@@ -39,7 +39,7 @@ CONFIGS = {
 }
 
 
-def config_inputs(cfg, progress=None, t0=0.0, cache=None):
+def preset_inputs(cfg, progress=None, t0=0.0, cache=None):
     """(H, E) float64 [3, nz, ny, nx] of a preset: the standing wave at t = 0 (phase
     offset t0), or the seeded random divergence-free fields of inputs.random_fields
     (about a minute per field at 512^3 on one core).  With cache (a directory), the
@@ -76,7 +76,7 @@ def _rel(d, scale):
     return d / scale if scale > 0 else d
 
 
-def run_config(i: int, steps=None, precs=None, progress=None, cache=None):
+def run_preset(i: int, steps=None, precs=None, progress=None, cache=None):
     """Step preset i in chunks of cfg['every'] steps; returns, per precision (and per
     phase offset t0 of the standing wave), the field-point-steps/s of the stepping
     (device-synchronised, readbacks excluded) and the drift of every invariant after each
@@ -85,14 +85,14 @@ def run_config(i: int, steps=None, precs=None, progress=None, cache=None):
     roundoffs of the precision per step; for the standing wave the error against the
     exact solution."""
     from . import eifp
-    cfg = CONFIGS[i]
+    cfg = PRESETS[i]
     steps = steps or cfg["steps"]
     every = min(cfg["every"], steps)
     dom = tuple(cfg["domain"])
-    out = {"config": i, "workload": cfg["workload"], "steps": steps, "every": every, "runs": {}}
+    out = {"preset": i, "workload": cfg["workload"], "steps": steps, "every": every, "runs": {}}
     t0s = cfg.get("t0", [0.0])
     for t0 in t0s:
-        H, E = config_inputs(cfg, progress, t0, cache)
+        H, E = preset_inputs(cfg, progress, t0, cache)
         for prec in precs or cfg["precs"]:
             label = prec if len(t0s) == 1 else f"{prec}_t0={t0:g}"
             with eifp.Solver(H, E, dom, cfg["mu"], cfg["eps"], prec) as warm:
@@ -149,12 +149,12 @@ def main():
     import argparse
     import json
     ap = argparse.ArgumentParser(description="run a named workload preset")
-    ap.add_argument("--config", type=int, required=True, choices=sorted(CONFIGS))
+    ap.add_argument("--preset", type=int, required=True, choices=sorted(PRESETS))
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--prec", default=None, help="comma list (default: the preset's)")
     ap.add_argument("--inputs-cache", default=None, help="directory for the generated random fields")
     a = ap.parse_args()
-    res = run_config(a.config, a.steps, a.prec.split(",") if a.prec else None,
+    res = run_preset(a.preset, a.steps, a.prec.split(",") if a.prec else None,
                      progress=lambda msg: print(msg, flush=True), cache=a.inputs_cache)
     print(json.dumps(res), flush=True)
 

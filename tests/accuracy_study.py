@@ -8,7 +8,7 @@ step of n tau from the same input (the scheme is exact in time, so stepping and 
 jump agree up to rounding).
 
 Run: python tests/accuracy_study.py --steps 2000 --every 100
-     python tests/accuracy_study.py --config 1     (128^3, FP64, 1000 steps, every 100)
+     python tests/accuracy_study.py --preset 1     (128^3, FP64, 1000 steps, every 100)
 It lives with the tests because it uses the oracle as its reference.
 """
 from __future__ import annotations
@@ -45,8 +45,8 @@ def run_preset(i: int, steps=None):
     """The same study on a named preset (its inputs, box, mu, eps, tau, step count and
     output interval), FP64 stepping only."""
     from paper_2210_06232_amd import workload
-    cfg = workload.CONFIGS[i]
-    H0, E0 = workload.config_inputs(cfg)
+    cfg = workload.PRESETS[i]
+    H0, E0 = workload.preset_inputs(cfg)
     return study(H0, E0, tuple(cfg["domain"]), cfg["mu"], cfg["eps"], cfg["tau"], steps or cfg["steps"],
                  cfg["every"], ("fp64_step",))
 
@@ -80,10 +80,10 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--every", type=int, default=100)
-    ap.add_argument("--config", type=int, default=None, help="a named preset (its own sizes and steps)")
+    ap.add_argument("--preset", type=int, default=None, help="a named preset (its own sizes and steps)")
     a = ap.parse_args()
-    if a.config is not None:
-        run_preset(a.config)
+    if a.preset is not None:
+        run_preset(a.preset)
     else:
         run(a.n, a.steps, a.every)
 
