@@ -197,7 +197,8 @@ const char *eifp_last_error(void);
  * memory budget and the batch has a free slot; new ones join a batch between chunks
  * of steps, so a request never waits for the whole batch to finish.  Each member's
  * arithmetic is independent of the others in its batch: a solve gives the same bits
- * alone and in any mix.
+ * alone and in any mix.  A request can be cancelled while queued or running; a failed
+ * batch ends only its own members.
  *
  * Threading: every server call may be made from any host thread; one internal thread
  * drives the GPU.
