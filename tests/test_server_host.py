@@ -261,7 +261,12 @@ def test_cancel_queued_and_running_requests():
         c = sv.submit(zeros(32), zeros(32), CUBE, nsteps=5, cadence=0, tag=3)
         wait_for(sv, lambda st: st["queued"] == 1)
         sv.cancel(c)
-        sv.cancel(c)  # again before its event: no-op
+        # again: a no-op while its event is pending; once the scheduler has ended it
+        # (which may already have happened), the id is unknown
+        try:
+            sv.cancel(c)
+        except m.EifpError as e:
+            assert e.status == m.EIFP_ERR_INVALID_ARG
         sv.cancel(a)
         wait_for(sv, lambda st: st["cancelled"] == 2 and st["running"] == 1 and st["queued"] == 0)
         d = sv.submit(zeros(32), zeros(32), CUBE, nsteps=5, cadence=0, tag=4)
