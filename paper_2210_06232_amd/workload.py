@@ -1,7 +1,9 @@
-"""The headline workload: one EI-FP step of a 256^3 grid on [0,2pi] x [0,4pi] x [0,2pi],
-mu = eps = 1, tau = 0.1, seeded random divergence-free fields with spectrum
-(1+|k|^2)^-2 cut at |k| <= 42.67 (the cut min_w(2 pi N_w / L_w)/3 of the recipe in
-inputs.random_divfree)."""
+"""The workloads: the headline one (one EI-FP step of a 256^3 grid on [0,2pi] x [0,4pi]
+x [0,2pi], mu = eps = 1, tau = 0.1, seeded random divergence-free fields with spectrum
+(1+|k|^2)^-2 cut at |k| <= 42.67, the cut min_w(2 pi N_w / L_w)/3 of the recipe in
+inputs.random_divfree), and named presets of the others with a runner that reports
+their point-step rate and the drift of every invariant
+(python -m paper_2210_06232_amd.workload --preset i)."""
 from __future__ import annotations
 
 import math
@@ -96,11 +98,11 @@ def run_preset(i: int, steps=None, precs=None, progress=None, cache=None):
         for prec in precs or cfg["precs"]:
             label = prec if len(t0s) == 1 else f"{prec}_t0={t0:g}"
             with eifp.Solver(H, E, dom, cfg["mu"], cfg["eps"], prec) as warm:
-                warm.step(cfg["tau"], every)  # builds the kernels and graphs of this shape
+                warm.step(cfg["tau"], every)  # first launches of this shape stay out of the timing
                 warm.sync()
             s = eifp.Solver(H, E, dom, cfg["mu"], cfg["eps"], prec)
             try:
-                out["runs"][label] = _run_one(s, cfg, steps, every, t0, prec, progress, f"config {i} {label}")
+                out["runs"][label] = _run_one(s, cfg, steps, every, t0, prec, progress, f"preset {i} {label}")
             finally:
                 s.close()
     return out
