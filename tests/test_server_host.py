@@ -291,3 +291,53 @@ def test_cancel_queued_and_running_requests():
             sv.cancel(k)
         assert ei.value.status == m.EIFP_ERR_STATE
         sv.release(k)
+
+
+def test_cancel_under_load_keeps_the_accounting():
+    # a stream of mixed requests with every third one cancelled at some point of its life
+    # (queued, running or already ended): every request ends exactly once, as done or
+    # cancelled, and all request memory returns to the budget
+    import random
+    m = eifp()
+    rng = random.Random(5)
+    fp = m.eifp_server_footprint(16, 16, 16, "fp64")
+    with m.Server(int(6.5 * fp), 3, m.EIFP_SERVER_DRY_RUN) as sv:
+        ids = []
+        for i in range(60):
+            n = (8, 16)[i % 2]
+            ids.append(sv.submit(zeros(n), zeros(n), CUBE, nsteps=rng.choice((5, 200, 10 ** 6)),
+                                 cadence=rng.choice((0, 50)), tag=i, prec=("fp64", "fp32")[i % 3 == 0]))
+        asked = set()
+        for rid in ids[::3]:
+            try:
+                sv.cancel(rid)
+                asked.add(rid)
+            except m.EifpError as e:  # already ended
+                assert e.status == m.EIFP_ERR_INVALID_ARG
+        # then cancel whatever is still live (the endless ones among them) so the stream ends
+        evs = []
+        for _ in range(200):
+            evs += sv.poll(4096, 10)
+            ended = {e["req_id"] for e in evs if e["kind"] in ("done", "error")}
+            live = [r for r in ids if r not in ended]
+            for rid in live:
+                try:
+                    sv.cancel(rid)
+                    asked.add(rid)
+                except m.EifpError:
+                    pass
+            if not live:
+                break
+        evs += drain_events(sv)
+        st = sv.stats()
+    by = events_by_request(evs)
+    assert sorted(by) == sorted(ids)
+    for rid, es in by.items():
+        ends = [e for e in es if e["kind"] in ("done", "error")]
+        assert len(ends) == 1 and es[-1] is ends[0], rid
+        if ends[0]["kind"] == "error":
+            assert ends[0]["status"] == m.EIFP_ERR_CANCELLED and rid in asked
+    assert st["completed"] + st["cancelled"] == 60 and st["failed"] == 0
+    assert st["running"] == 0 and st["queued"] == 0
+    # what stays in use is the batch tables of idle groups, less than one request
+    assert st["bytes_in_use"] < fp and st["peak_bytes"] <= int(6.5 * fp)
