@@ -37,3 +37,11 @@ def test_traffic_lookup_follows_the_source_hash(tmp_path, monkeypatch):
     (tmp_path / "profiles" / "traffic_256cubed.json").write_text(json.dumps(stale))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_traffic("fp64", "k_fused") is None
+
+
+def test_oracle_timing_script_runs_on_a_small_grid():
+    # the all-core oracle timing (tests/oracle_timing.py) on a 16^3 sample, 2 processes
+    from tests import oracle_timing
+    out = oracle_timing.run(2, 16)
+    assert out["single"]["value"] > 0 and out["parallel"]["processes"] == 2
+    assert out["parallel"]["value"] > 0 and out["parallel"]["wall_s"] > 0
