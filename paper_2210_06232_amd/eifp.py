@@ -460,6 +460,7 @@ class Server:
         eifp_server_release(self.handle, req_id)
 
     def cancel(self, req_id):
+        """End a queued or running request (its last event: error, status CANCELLED)."""
         eifp_server_cancel(self.handle, req_id)
 
     def stats(self) -> dict:
