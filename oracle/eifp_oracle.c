@@ -297,24 +297,45 @@ void orc_coefficients(double bx, double by, double bz, double kappa, double *c, 
     s[2] = kappa * bx * r2;                       /* s23 / i */
 }
 
-/* The mode-wise 6x6 map (Hx,Hy,Hz,Ex,Ey,Ez)^ at time 0 -> at time t of Alg. 2 step 4:
- * scale H by sqrt(mu), E by sqrt(eps), mix with the c and s coefficients, unscale.
- * P is row-major 6x6 complex, interleaved (72 doubles). */
+/* Prop. 2.2 in block form.  On the scaled coefficients (u, v) = (sqrt(mu) H^, sqrt(eps) E^)
+ * one mode evolves by the 6x6 matrix
+ *       [  C  S ]        C = [c11 c12 c13]        S = [  0    s12  -s13 ]
+ *       [ -S  C ]            [c12 c22 c23]            [ -s12   0    s23 ]
+ *                            [c13 c23 c33]            [  s13 -s23    0  ]
+ * with C real symmetric and S purely imaginary and skew (the s_ij of Prop. 2.2 carry the
+ * factor i).  c[6], s[3] are as returned by orc_coefficients. */
+static void scaled_block(const double *c, const double *s, cplx M[6][6])
+{
+    const double C[3][3] = {{c[0], c[1], c[2]}, {c[1], c[3], c[4]}, {c[2], c[4], c[5]}};
+    const cplx S[3][3] = {{0, I * s[0], -I * s[1]}, {-I * s[0], 0, I * s[2]}, {I * s[1], -I * s[2], 0}};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            M[i][j] = C[i][j];
+            M[i][3 + j] = S[i][j];
+            M[3 + i][j] = -S[i][j];
+            M[3 + i][3 + j] = C[i][j];
+        }
+}
+
+/* y = M x for one mode (6 complex coefficients). */
+static void apply_block(cplx M[6][6], const cplx *x, cplx *y)
+{
+    for (int i = 0; i < 6; ++i) {
+        cplx acc = 0;
+        for (int j = 0; j < 6; ++j) acc += M[i][j] * x[j];
+        y[i] = acc;
+    }
+}
+
+/* The mode-wise 6x6 map (Hx,Hy,Hz,Ex,Ey,Ez)^ at time 0 -> at time t (Prop. 2.1/2.2,
+ * Alg. 2 step 4): the scaled block above, conjugated by the diagonal scaling
+ * diag(sqrt(mu) I, sqrt(eps) I).  P is row-major 6x6 complex, interleaved (72 doubles). */
 void orc_propagator(double bx, double by, double bz, double t, double mu, double eps, double *P)
 {
     double c[6], s[3];
+    cplx M[6][6];
     orc_coefficients(bx, by, bz, t / sqrt(mu * eps), c, s);
-    const double c11 = c[0], c12 = c[1], c13 = c[2], c22 = c[3], c23 = c[4], c33 = c[5];
-    const cplx s12 = I * s[0], s13 = I * s[1], s23 = I * s[2];
-    /* scaled map on (u, v) = (sqrt(mu) H^, sqrt(eps) E^) */
-    cplx M[6][6] = {
-        {c11, c12, c13, 0, s12, -s13},
-        {c12, c22, c23, -s12, 0, s23},
-        {c13, c23, c33, s13, -s23, 0},
-        {0, -s12, s13, c11, c12, c13},
-        {s12, 0, -s23, c12, c22, c23},
-        {-s13, s23, 0, c13, c23, c33},
-    };
+    scaled_block(c, s, M);
     const double sc[6] = {sqrt(mu), sqrt(mu), sqrt(mu), sqrt(eps), sqrt(eps), sqrt(eps)};
     cplx *out = (cplx *)P;
     for (int i = 0; i < 6; ++i)
@@ -369,21 +390,13 @@ int orc_step(int nx, int ny, int nz, const double *dom, double mu, double eps, d
                 f[(3 + c) * ns + q] = E[c * ns + q];
             }
         for (int c = 0; c < 6; ++c) orc_fft3(nx, ny, nz, (double *)(f + c * ns), -1);
-        /* Alg. 2 step 4: scale, mix, unscale */
+        /* Alg. 2 step 4: scale to (u, v), apply the mode's block of Prop. 2.2, unscale */
         for (long q = 0; q < ns; ++q) {
-            const double *cc = cf + 9 * q;
-            const double c11 = cc[0], c12 = cc[1], c13 = cc[2], c22 = cc[3], c23 = cc[4], c33 = cc[5];
-            const cplx s12 = I * cc[6], s13 = I * cc[7], s23 = I * cc[8];
-            const cplx ux = smu * f[0 * ns + q], uy = smu * f[1 * ns + q], uz = smu * f[2 * ns + q];
-            const cplx vx = seps * f[3 * ns + q], vy = seps * f[4 * ns + q], vz = seps * f[5 * ns + q];
-            const cplx hx = c11 * ux + c12 * uy + c13 * uz + s12 * vy - s13 * vz;
-            const cplx hy = c12 * ux + c22 * uy + c23 * uz - s12 * vx + s23 * vz;
-            const cplx hz = c13 * ux + c23 * uy + c33 * uz + s13 * vx - s23 * vy;
-            const cplx ex = c11 * vx + c12 * vy + c13 * vz - s12 * uy + s13 * uz;
-            const cplx ey = c12 * vx + c22 * vy + c23 * vz + s12 * ux - s23 * uz;
-            const cplx ez = c13 * vx + c23 * vy + c33 * vz - s13 * ux + s23 * uy;
-            f[0 * ns + q] = hx / smu; f[1 * ns + q] = hy / smu; f[2 * ns + q] = hz / smu;
-            f[3 * ns + q] = ex / seps; f[4 * ns + q] = ey / seps; f[5 * ns + q] = ez / seps;
+            cplx M[6][6], x[6], y[6];
+            scaled_block(cf + 9 * q, cf + 9 * q + 6, M);
+            for (int c = 0; c < 6; ++c) x[c] = (c < 3 ? smu : seps) * f[c * ns + q];
+            apply_block(M, x, y);
+            for (int c = 0; c < 6; ++c) f[c * ns + q] = y[c] / (c < 3 ? smu : seps);
         }
         /* Alg. 2 step 5: inverse transform; the result is real up to rounding */
         for (int c = 0; c < 6; ++c) orc_fft3(nx, ny, nz, (double *)(f + c * ns), 1);
