@@ -56,7 +56,9 @@ struct Engine {
     int nparts = 0;  // partial records per member
     long long bytes = 0;
 
-    eifp_status init(int nx, int ny, int nz, eifp_precision p);
+    // allocate the tables and form them on the device (enqueued on stream, which is then
+    // synchronised)
+    eifp_status init(int nx, int ny, int nz, eifp_precision p, hipStream_t stream = nullptr);
     void release();
     size_t state_bytes() const { return (size_t)6 * (size_t)ns * tsize; }
     // room for the extended record (INV_XPART doubles per workgroup)
@@ -82,6 +84,16 @@ struct Engine {
     // with the invariants if want_inv.
     eifp_status jump(const void* md, int nm, hipStream_t st, bool want_inv = true) const;
 };
+
+// Bytes of the twiddle table of length n: n entries exp(-2 pi i k / n), plus their
+// rounding remainders for FP32 tables.
+template <typename T>
+constexpr size_t twiddle_table_bytes(int n) {
+    return (size_t)n * TwParts<T>::value * sizeof(cpx<T>);
+}
+// Form that table at tw on the device (k_twiddles, enqueued on st).
+template <typename T>
+eifp_status launch_twiddles(cpx<T>* tw, int n, hipStream_t st);
 
 // Widen / narrow n reals on the device (enqueued on st).
 eifp_status convert_f32_to_f64(const void* in, void* out, long long n, hipStream_t st);

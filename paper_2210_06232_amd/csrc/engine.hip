@@ -22,29 +22,15 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kPi = 3.141592653589793238462643383279502884;
 
 template <typename T>
-eifp_status upload_table(void** dst, int n, long long* bytes) {
-    // exp(-2 pi i k / n), k < n, formed in FP64 and rounded to T; an FP32 table carries
-    // the rounding remainders (FP64 value - rounded value, rounded) as entries n..2n-1
-    const int parts = TwParts<T>::value;
-    std::vector<T> h(2 * (size_t)n * parts);
-    for (int k = 0; k < n; ++k) {
-        const double a = kTwoPi * (double)k / (double)n;
-        const double c = std::cos(a), s = -std::sin(a);
-        h[2 * k] = (T)c;
-        h[2 * k + 1] = (T)s;
-        if (parts == 2) {
-            h[2 * (n + k)] = (T)(c - (double)h[2 * k]);
-            h[2 * (n + k) + 1] = (T)(s - (double)h[2 * k + 1]);
-        }
-    }
-    if (hipMalloc(dst, h.size() * sizeof(T)) != hipSuccess) {
+eifp_status make_table(void** dst, int n, long long* bytes, hipStream_t st) {
+    const size_t nb = twiddle_table_bytes<T>(n);
+    if (hipMalloc(dst, nb) != hipSuccess) {
         *dst = nullptr;
         (void)hipGetLastError();
         return fail(EIFP_ERR_OUT_OF_MEMORY, "twiddle table allocation failed");
     }
-    *bytes += (long long)(h.size() * sizeof(T));
-    EIFP_HIP_TRY(hipMemcpy(*dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
-    return EIFP_OK;
+    *bytes += (long long)nb;
+    return launch_twiddles<T>((cpx<T>*)*dst, n, st);
 }
 
 eifp_status rc_to_status(int rc, const char* what) {
@@ -206,7 +192,7 @@ PropParams make_params(int nx, int ny, int nz, const eifp_domain& dom, double mu
     return pp;
 }
 
-eifp_status Engine::init(int nx, int ny, int nz, eifp_precision p) {
+eifp_status Engine::init(int nx, int ny, int nz, eifp_precision p, hipStream_t stream) {
     g = Grid3{nx, ny, nz, nx / 2};
     prec = p;
     tsize = p == EIFP_FP64 ? 8 : 4;
@@ -215,14 +201,15 @@ eifp_status Engine::init(int nx, int ny, int nz, eifp_precision p) {
     if (nparts <= 0) return fail(EIFP_ERR_UNSUPPORTED_SIZE, "no compiled plan for ny = %d", ny);
     eifp_status st = EIFP_OK;
     if (p == EIFP_FP64) {
-        if ((st = upload_table<double>(&twx, nx, &bytes)) || (st = upload_table<double>(&twy, ny, &bytes)) ||
-            (st = upload_table<double>(&twz, nz, &bytes)))
+        if ((st = make_table<double>(&twx, nx, &bytes, stream)) || (st = make_table<double>(&twy, ny, &bytes, stream)) ||
+            (st = make_table<double>(&twz, nz, &bytes, stream)))
             return st;
     } else {
-        if ((st = upload_table<float>(&twx, nx, &bytes)) || (st = upload_table<float>(&twy, ny, &bytes)) ||
-            (st = upload_table<float>(&twz, nz, &bytes)))
+        if ((st = make_table<float>(&twx, nx, &bytes, stream)) || (st = make_table<float>(&twy, ny, &bytes, stream)) ||
+            (st = make_table<float>(&twz, nz, &bytes, stream)))
             return st;
     }
+    EIFP_HIP_TRY(hipStreamSynchronize(stream));
     return EIFP_OK;
 }
 
@@ -251,6 +238,16 @@ eifp_status Engine::jump(const void* md, int nm, hipStream_t st, bool want_inv) 
     return prec == EIFP_FP64 ? run_jump<double>(*this, md, nm, st, want_inv)
                              : run_jump<float>(*this, md, nm, st, want_inv);
 }
+
+template <typename T>
+eifp_status launch_twiddles(cpx<T>* tw, int n, hipStream_t st) {
+    const int blocks = (n + 255) / 256;
+    hipLaunchKernelGGL((k_twiddles<T>), dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, tw, n);
+    if (hipGetLastError() != hipSuccess) return fail(EIFP_ERR_DEVICE, "twiddle table kernel launch failed");
+    return EIFP_OK;
+}
+template eifp_status launch_twiddles<double>(cpx<double>*, int, hipStream_t);
+template eifp_status launch_twiddles<float>(cpx<float>*, int, hipStream_t);
 
 eifp_status convert_f32_to_f64(const void* in, void* out, long long n, hipStream_t st) {
     return convert<double, float>(in, out, n, st);

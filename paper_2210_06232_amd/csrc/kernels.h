@@ -1204,6 +1204,25 @@ k_fused_split(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx,
     if (want_inv) block_reduce_store<NT, Q>(acc, mem.partials + (long)blockIdx.x * Q, s_red);
 }
 
+// Twiddle table of length n: tw[k] = exp(-2 pi i k / n) for k < n, formed in FP64 and
+// rounded to T; an FP32 table also holds the rounding remainders (FP64 value minus the
+// rounded value, rounded) at tw[n + k].  Every table the library uses comes from here.
+template <typename T>
+__device__ __forceinline__ void form_twiddle(cpx<T>* __restrict__ tw, int n, int k) {
+    const double a = 6.283185307179586476925286766559 * (double)k / (double)n;
+    double sn, cs;
+    sincos(a, &sn, &cs);
+    sn = -sn;
+    const cpx<T> hi = {(T)cs, (T)sn};
+    tw[k] = hi;
+    if constexpr (TwParts<T>::value == 2) tw[n + k] = {(T)(cs - (double)hi.x), (T)(sn - (double)hi.y)};
+}
+template <typename T>
+__global__ void __launch_bounds__(256) k_twiddles(cpx<T>* __restrict__ tw, int n) {
+    const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k < n) form_twiddle(tw, n, k);
+}
+
 // FP64 <-> T conversion for upload / download of the state.
 template <typename TO, typename TI>
 __global__ void __launch_bounds__(256) k_convert(const TI* __restrict__ in, TO* __restrict__ out, long n) {

@@ -206,7 +206,7 @@ eifp_status group_alloc(Group* g, int max_batch) {
     EIFP_HIP_TRY(hipStreamCreateWithFlags(&g->st, hipStreamNonBlocking));
     EIFP_HIP_TRY(hipEventCreate(&g->ev0));
     EIFP_HIP_TRY(hipEventCreate(&g->ev1));
-    eifp_status st = g->en.init(g->key.nx, g->key.ny, g->key.nz, (eifp_precision)g->key.prec);
+    eifp_status st = g->en.init(g->key.nx, g->key.ny, g->key.nz, (eifp_precision)g->key.prec, g->st);
     if (st) return st;
     g->nparts = g->en.nparts;
     const size_t pb = (size_t)max_batch * g->nparts * INV_NPART * sizeof(double);

@@ -159,7 +159,7 @@ eifp_status eifp_init(eifp_solver** out, int nx, int ny, int nz, const eifp_doma
         INIT_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
         s->own_stream = true;
     }
-    INIT_TRY(s->en.init(nx, ny, nz, prec));
+    INIT_TRY(s->en.init(nx, ny, nz, prec, s->stream));
     const size_t sb = s->en.state_bytes();
     INIT_TRY(alloc(&s->state, sb, &s->bytes));
     INIT_TRY(alloc(&s->scratch, sb, &s->bytes));

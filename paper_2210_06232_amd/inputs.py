@@ -178,3 +178,37 @@ def white_noise_fields(shape, seed: int):
     H = rng.standard_normal((3, nz, ny, nx))
     E = rng.standard_normal((3, nz, ny, nx))
     return H, E
+
+
+def upsample_bandlimited(F, fine_shape, workers: int | None = None) -> np.ndarray:
+    """The trigonometric interpolant of a real grid field [3, nz, ny, nx] sampled on a
+    finer grid (fine_shape = (Nx, Ny, Nz), each a multiple of the coarse size), by
+    zero-padding its spectrum.  The coarse field must carry nothing at its Nyquist
+    indices (the random fields above never do); its values at the shared points are
+    then reproduced up to rounding, and the fine field is band-limited to the coarse
+    grid's modes.  Used to build embedding inputs: a band-limited field evolves the same
+    on both grids, so the fine solution at the shared points is the coarse one."""
+    import os
+
+    import scipy.fft as sfft
+
+    F = np.asarray(F, dtype=np.float64)
+    _, nz, ny, nx = F.shape
+    Nx, Ny, Nz = fine_shape
+    if Nx % nx or Ny % ny or Nz % nz:
+        raise ValueError("fine grid sizes must be multiples of the coarse ones")
+    w = workers or max(1, min(16, os.cpu_count() or 1))
+    # signed coarse indices (Nyquist dropped) -> positions on the fine grid
+    zi = np.r_[0:nz // 2, nz // 2 + 1:nz]
+    yi = np.r_[0:ny // 2, ny // 2 + 1:ny]
+    zf = np.where(zi < nz // 2, zi, Nz - (nz - zi))
+    yf = np.where(yi < ny // 2, yi, Ny - (ny - yi))
+    out = np.empty((3, Nz, Ny, Nx))
+    scale = (Nx * Ny * Nz) / (nx * ny * nz)
+    for c in range(3):
+        G = sfft.rfftn(F[c], workers=w)
+        Gp = np.zeros((Nz, Ny, Nx // 2 + 1), dtype=np.complex128)
+        Gp[np.ix_(zf, yf, np.arange(nx // 2))] = G[np.ix_(zi, yi, np.arange(nx // 2))]
+        out[c] = sfft.irfftn(Gp, s=(Nz, Ny, Nx), workers=w) * scale
+        del G, Gp
+    return out

@@ -35,3 +35,14 @@ def energy_rel_error(H, E, Hx, Ex, mu, eps):
     num = mu * norm_n(np.asarray(H) - Hx) ** 2 + eps * norm_n(np.asarray(E) - Ex) ** 2
     den = mu * norm_n(Hx) ** 2 + eps * norm_n(Ex) ** 2
     return float(np.sqrt(num / den))
+
+
+def elementwise_rel_error(H, E, Hx, Ex, mu, eps):
+    """Largest pointwise error over all six components, relative to the largest value
+    of the reference, both in the energy weighting (sqrt(mu) H, sqrt(eps) E).  A local
+    mistake (one bad tile, plane or pencil) shows here even when it barely moves the
+    global energy norm."""
+    sm, se = float(np.sqrt(mu)), float(np.sqrt(eps))
+    err = max(sm * float(np.max(np.abs(np.asarray(H) - Hx))), se * float(np.max(np.abs(np.asarray(E) - Ex))))
+    ref = max(sm * float(np.max(np.abs(Hx))), se * float(np.max(np.abs(Ex))))
+    return err / ref

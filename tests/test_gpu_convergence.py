@@ -33,3 +33,23 @@ def test_resolved_data_is_exact():
         Hc, Ec = s.fields()
     err = convergence.energy_error(Hc, Ec, convergence.subsample(Hf, 16), convergence.subsample(Ef, 16), 1.0, 1.5)
     assert err < 1e-13
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_coarse_jumps_match_oracle(n):
+    # the study's coarse runs: the GPU jump of the subsampled data equals the oracle's one
+    # step over the same span on the same input, so every error in the study is measured
+    # on an oracle-checked path
+    from oracle import oracle as orc
+    from paper_2210_06232_amd import eifp
+    from tests.helpers import elementwise_rel_error
+    dom = (0.0, 2 * math.pi, 0.0, 2 * math.pi, 0.0, 2 * math.pi)
+    mu, eps, t_end = 1.0, 1.5, 1.0
+    H0, E0 = convergence.reference_fields(64, 1.5, dom, 7000)
+    Hc, Ec = convergence.subsample(H0, n), convergence.subsample(E0, n)
+    with eifp.Solver(Hc, Ec, dom, mu, eps, "fp64") as s:
+        s.jump(t_end, 1)
+        Hg, Eg = s.fields()
+    Ho, Eo, _ = orc.step(Hc, Ec, dom, mu, eps, t_end, 1)
+    assert convergence.energy_error(Hg, Eg, Ho, Eo, mu, eps) <= 1e-12
+    assert elementwise_rel_error(Hg, Eg, Ho, Eo, mu, eps) <= 1e-12

@@ -10,7 +10,7 @@ import pytest
 
 from oracle import oracle as orc
 from paper_2210_06232_amd import inputs
-from tests.helpers import energy_rel_error
+from tests.helpers import elementwise_rel_error, energy_rel_error
 
 pytestmark = pytest.mark.gpu
 
@@ -146,9 +146,14 @@ def test_mix_matches_oracle():
         H, E = fields_of(case)
         Ho, Eo, _ = orc.step(H, E, dom, mu, eps, tau, nsteps)
         Hg, Eg, _, _ = mix[i]
-        # FP32: local error plus the linear growth of the per-step round trip
-        tol = FP64_TOL if prec == "fp64" else FP32_TOL + 1e-7 * nsteps
-        assert energy_rel_error(Hg, Eg, Ho, Eo, mu, eps) <= tol, (i, prec)
+        # every FP32 rounding of a constant is compensated, so the FP32 error grows like the
+        # square root of the step count and these runs (at most 51 steps) stay inside the
+        # stated tolerance
+        tol = FP64_TOL if prec == "fp64" else FP32_TOL
+        en = energy_rel_error(Hg, Eg, Ho, Eo, mu, eps)
+        el = elementwise_rel_error(Hg, Eg, Ho, Eo, mu, eps)
+        print(f"case {i} {prec} {nsteps} steps: energy-norm {en:.3e}, element-wise {el:.3e}")
+        assert en <= tol and el <= tol, (i, prec, en, el)
 
 
 def test_graphs_and_eager_launches_agree_bitwise():
