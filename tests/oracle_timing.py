@@ -1,10 +1,10 @@
-"""Host throughput of the CPU oracle on the headline workload (one step of the 256^3
-grid, FP64): once on one thread, and as P concurrent single-threaded processes, each
-stepping the same input (the oracle has no threads of its own; P defaults to the
-smaller of the host's CPU count and 16).  The aggregate rate is P x N^3 / wall time.
-It is a reported baseline for the GPU figures, not a target.
+"""Host throughput of the CPU oracle (FP64): S steps of an N^3 grid on the headline box,
+once on one thread, and as P concurrent single-threaded processes, each stepping the
+same input (the oracle has no threads of its own; P defaults to the smaller of the
+host's CPU count and 16).  The aggregate rate is P x S x N^3 / wall time.  It is a
+reported baseline for the GPU figures, not a target.
 
-Run: python tests/oracle_timing.py [--procs P] [--n N]
+Run: python tests/oracle_timing.py [--procs P] [--n N] [--steps S]
 It lives with the tests because it runs the oracle.
 """
 from __future__ import annotations
@@ -21,6 +21,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 _FIELDS = None  # inherited by forked workers
+_STEPS = 1
 
 
 def _one_step(_):
@@ -28,7 +29,7 @@ def _one_step(_):
     from paper_2210_06232_amd.workload import HEADLINE
     H, E = _FIELDS
     t0 = time.perf_counter()
-    orc.step(H, E, tuple(HEADLINE["domain"]), HEADLINE["mu"], HEADLINE["eps"], HEADLINE["tau"], 1)
+    orc.step(H, E, tuple(HEADLINE["domain"]), HEADLINE["mu"], HEADLINE["eps"], HEADLINE["tau"], _STEPS)
     return time.perf_counter() - t0
 
 
@@ -45,12 +46,13 @@ def host():
     return {"model": model, "nproc": os.cpu_count()}
 
 
-def run(procs: int, n: int):
-    global _FIELDS
+def run(procs: int, n: int, steps: int = 1):
+    global _FIELDS, _STEPS
+    _STEPS = steps
     from paper_2210_06232_amd import inputs
     from paper_2210_06232_amd.workload import HEADLINE
     _FIELDS = inputs.random_fields((n, n, n), tuple(HEADLINE["domain"]), workload=2, p=2.0)
-    pts = n ** 3
+    pts = n ** 3 * steps
     single = _one_step(0)
     print(f"[oracle timing] one thread: {single:.2f} s", flush=True)
     ctx = mp.get_context("fork")
@@ -59,6 +61,7 @@ def run(procs: int, n: int):
         each = pool.map(_one_step, range(procs), chunksize=1)
         wall = time.perf_counter() - t0
     out = {"workload": HEADLINE["workload"] if n == HEADLINE["grid"][0] else f"{n}^3 sample of the headline box",
+           "steps": steps,
            "unit": "field-point-steps/s",
            "single": {"threads": 1, "seconds": round(single, 2), "value": pts / single},
            "parallel": {"processes": procs, "wall_s": round(wall, 2), "max_process_s": round(max(each), 2),
@@ -72,8 +75,9 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--procs", type=int, default=min(os.cpu_count() or 1, 16))
     ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=1)
     a = ap.parse_args()
-    run(a.procs, a.n)
+    run(a.procs, a.n, a.steps)
 
 
 if __name__ == "__main__":

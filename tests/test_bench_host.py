@@ -45,3 +45,14 @@ def test_oracle_timing_script_runs_on_a_small_grid():
     out = oracle_timing.run(2, 16)
     assert out["single"]["value"] > 0 and out["parallel"]["processes"] == 2
     assert out["parallel"]["value"] > 0 and out["parallel"]["wall_s"] > 0
+
+
+def test_cpu_baseline_reports_one_thread_and_all_processes():
+    # the bench's CPU leg on a 16^3 input: one-thread rate beside the concurrent-process rate
+    import bench
+    from paper_2210_06232_amd import inputs
+    H, E = inputs.random_fields((16, 16, 16), tuple(bench.WORKLOAD["domain"]), workload=2, p=2.0)
+    out = bench.cpu_baseline(H, E)
+    assert out["kind"] == "oracle" and out["cores"] >= 1 and out["value"] > 0
+    assert out["single_thread"]["cores"] == 1 and out["single_thread"]["value"] > 0
+    assert "16^3" in out["sample"] and out["seconds"] > 0
