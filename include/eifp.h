@@ -333,6 +333,36 @@ eifp_status eifp_server_drain(eifp_server *sv, int timeout_ms);
  * NULL is accepted. */
 eifp_status eifp_server_destroy(eifp_server *sv);
 
+/* ---------------------------------------------------------------------------------
+ * Allocation-free stepping
+ * ---------------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): eifp_step's time steps applied in
+ * place to a caller-owned device state, with no solver object and no device allocation.
+ * The library's own working data for the call (member descriptor, twiddle tables, the
+ * fused pass's partial sums, the invariant record) lives in a fixed 4 MiB device array
+ * that each GPU the library runs on holds until the process ends; every supported grid
+ * fits in it, and a grid that would not is rejected with UNSUPPORTED_SIZE before anything
+ * is enqueued.  The call only enqueues work (a set-up kernel, then the passes of each
+ * step); it makes no hipMalloc/hipFree and does not synchronise.  All calls on one GPU
+ * share that array: calls whose work overlaps on the device race and must be ordered by
+ * the caller (one stream, or events).  Results equal eifp_init + eifp_step +
+ * eifp_fields_device of the same fields, in the same precision.
+ *   fields    device buffer, 16-byte aligned, of 6*nx*ny*nz elements of the working
+ *             precision (double for EIFP_FP64, float for EIFP_FP32): Hx, Hy, Hz, Ex, Ey,
+ *             Ez, each [nz][ny][nx] with x fastest; read and overwritten in place
+ *   nx..prec  as eifp_init; tau, nsteps as eifp_step (nsteps = 0 enqueues nothing)
+ *   inv_out   NULL, or a device buffer of 8 doubles that receives the invariants of the
+ *             final state: E1, H1, M1x, M1y, M1z, ||div~(mu H)||_N, ||div~(eps E)||_N, 0
+ *             (eifp_invariant_set's order; reduced on the last step only)
+ *   hip_stream  the hipStream_t to enqueue on (NULL: the null stream)
+ * Errors (all detected on the host before anything is enqueued): INVALID_ARG (NULL or
+ * misaligned pointers, pointers that are not device memory or whose allocation is too
+ * short, sizes, domain, mu, eps, tau, nsteps < 0, unknown precision), UNSUPPORTED_SIZE,
+ * DEVICE (a failed launch). */
+eifp_status eifp_step_noalloc(void *fields, int nx, int ny, int nz, const eifp_domain *dom, double mu, double eps,
+                              eifp_precision prec, double tau, long long nsteps, double *inv_out, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

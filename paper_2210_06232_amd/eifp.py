@@ -145,6 +145,9 @@ SIGNATURES = {
     "eifp_server_stats": (ctypes.c_int, [_VP, ctypes.POINTER(eifp_server_stat_set)]),
     "eifp_server_drain": (ctypes.c_int, [_VP, ctypes.c_int]),
     "eifp_server_destroy": (ctypes.c_int, [_VP]),
+    "eifp_step_noalloc": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(eifp_domain),
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_longlong, _VP, _VP]),
 }
 
 _lib = None
@@ -293,6 +296,18 @@ def eifp_device_bytes(handle) -> int:
 
 def eifp_destroy(handle):
     _check(load().eifp_destroy(handle), "eifp_destroy")
+
+
+def eifp_step_noalloc(fields_ptr: int, shape, domain, mu, eps, prec, tau, nsteps=1, inv_ptr: int = 0,
+                      stream: int = 0):
+    """Step a caller-owned device state [6, nz, ny, nx] (in the working precision) in
+    place, with no device allocation; shape = (nx, ny, nz).  Enqueues only."""
+    nx, ny, nz = shape
+    p = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    dom = eifp_domain(*[float(v) for v in domain])
+    _check(load().eifp_step_noalloc(fields_ptr or None, int(nx), int(ny), int(nz), ctypes.byref(dom), float(mu),
+                                    float(eps), p, float(tau), int(nsteps), inv_ptr or None, stream or None),
+           "eifp_step_noalloc")
 
 
 # ----------------------------------------------------------------------------------
