@@ -270,10 +270,14 @@ int count_fused(int axis, const Grid3& g) {
     return axis == AXIS_Y ? fused_workgroups<T, N, AXIS_Y>(g) : -1;
 }
 
-// axis lengths compiled for y and z
+// axis lengths compiled for y and z (a build may list fewer, e.g. to time one size)
+#ifndef EIFP_AXIS_SIZES
 #define EIFP_AXIS_SIZES(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+#endif
 // half lengths M = Nx/2 compiled for x
+#ifndef EIFP_HALF_SIZES
 #define EIFP_HALF_SIZES(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+#endif
 
 inline int axis_len(int axis, const Grid3& g) { return axis == AXIS_Y ? g.ny : g.nz; }
 
