@@ -81,6 +81,7 @@ def run_gpu_pair(H, E, steps: int, warmup: int):
         for s in (s32, s64):
             if warmup:
                 s.step(WORKLOAD["tau"], warmup)
+                s.sync()  # one form at a time: the two solvers' streams never share the device
         t64 = timed_steps(s64, steps)
         t32 = timed_steps(s32, steps)
         inv64, inv32 = s64.invariants(), s32.invariants()
@@ -298,6 +299,8 @@ def main():
         "step_hbm_gbs": r64["step_hbm_gbs"],
         "step_counted_gbs": r64["step_counted_gbs"],
         "step_counted_frac": r64["step_counted_frac"],
+        "step_counted_note": "FETCH_SIZE/WRITE_SIZE count L2-to-fabric traffic, reads served by the 256 MB "
+                             "last-level cache (MALL) included; gfx950 exposes no counter below the L2",
         "pass_ms_per_step": r64["pass_ms_per_step"],
         "fp32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
                  "roofline": r32["roofline"], "pass_ms_per_step": r32["pass_ms_per_step"],

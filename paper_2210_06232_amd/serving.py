@@ -60,7 +60,7 @@ def add_arrivals(reqs, rate: float, seed: int = STREAM_SEED + 1):
     return reqs
 
 
-def field_pools(reqs, pool: int):
+def field_pools(reqs, pool: int, progress=None):
     """{(shape, index): (H, E)} for every pair the stream uses."""
     out = {}
     for r in reqs:
@@ -68,6 +68,8 @@ def field_pools(reqs, pool: int):
         if key not in out:
             sid = 4000 + 10 * STREAM_SHAPES.index(r["shape"]) + r["pool_index"]
             out[key] = inputs.random_fields(r["shape"], r["domain"], workload=sid, p=2.0)
+            if progress:
+                progress(f"  fields {len(out)}: {key[0]} #{key[1]}")
     return out
 
 
@@ -154,20 +156,25 @@ def replay(reqs, pools, budget: int, max_batch: int = 32, flags: int = 0, force_
 
 
 def run_stream(n_requests=64, load=0.8, pool=1, budget=24 * 10 ** 9, max_batch=32, modes=("batched", "serial_own",
-               "serial_fp64"), max_steps=5000, progress=None, burst=False):
+               "serial_fp64"), max_steps=5000, progress=None, burst=False, rate=None):
     """Replay one seeded stream in each mode.  burst: every request arrives at t = 0
     (saturation: aggregate throughput); otherwise Poisson arrivals at `load` times the
-    one-at-a-time capacity (latency)."""
+    one-at-a-time capacity (latency), or at a given `rate` per second (then runs made
+    separately, e.g. one mode per run, replay the same arrival times: the arrivals are
+    seeded and depend only on the rate)."""
     reqs = make_stream(n_requests, pool=pool, max_steps=max_steps)
-    pools = field_pools(reqs, pool)
+    pools = field_pools(reqs, pool, progress)
     step_s = calibrate(pools)
     mean_service = float(np.mean([service_time(r, step_s) for r in reqs]))
-    rate = load / mean_service
+    if rate is None:
+        rate = load / mean_service
+    else:
+        load = rate * mean_service  # the offered load this rate means on this GPU
     add_arrivals(reqs, rate)
     if burst:
         for r in reqs:
             r["arrival"] = 0.0
-    out = {"requests": n_requests, "load": None if burst else load, "burst": burst,
+    out = {"requests": n_requests, "load": None if burst else round(load, 4), "burst": burst,
            "rate_per_s": None if burst else rate, "mean_service_s": mean_service, "pool": pool,
            "max_steps": max_steps, "budget_bytes": budget, "max_batch": max_batch,
            "step_ms": {f"{s[0]}x{s[1]}x{s[2]}_{p}": round(v * 1e3, 4) for (s, p), v in sorted(step_s.items())}}
@@ -196,9 +203,11 @@ def main():
     ap.add_argument("--modes", default="batched,serial_own,serial_fp64",
                     help="comma list of batched, batched_no_graphs, serial_own, serial_fp64, anchored")
     ap.add_argument("--burst", action="store_true", help="every request arrives at t = 0")
+    ap.add_argument("--rate", type=float, default=None,
+                    help="arrivals per second (instead of --load), so that separate runs share one schedule")
     a = ap.parse_args()
     res = run_stream(a.requests, a.load, a.pool, int(a.budget_gb * 1e9), a.max_batch, tuple(a.modes.split(",")),
-                     a.max_steps, progress=lambda s: print(s, flush=True), burst=a.burst)
+                     a.max_steps, progress=lambda s: print(s, flush=True), burst=a.burst, rate=a.rate)
     print(json.dumps(res))
 
 
