@@ -18,7 +18,9 @@
  *   - Every call returns an eifp_status; on failure eifp_last_error() gives a
  *     thread-local description.  No call throws or aborts.
  *   - Host pointers are only read during the call that receives them; the library
- *     never keeps them.  All device memory is owned by the library.
+ *     never keeps them.  Device memory the library allocates is owned by it; the
+ *     caller's device buffers (eifp_fields_device, eifp_step_noalloc) stay the
+ *     caller's and are only used by the work that call enqueues.
  *   - One solver may be used by one host thread at a time.
  */
 #ifndef EIFP_H
