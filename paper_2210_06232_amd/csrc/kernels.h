@@ -591,6 +591,45 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[Q], double* __r
     }
 }
 
+// sin(pi x) and cos(pi x) in FP64, from the Taylor series of sin and cos: x = n/2 + r with
+// n = rint(2x) and |r| <= 1/4 (n/2 and r are exact in FP64), sin(pi r) and cos(pi r) by
+// Horner in r^2 through the terms of degree 17 and 16 (the first terms left out are below
+// 1e-19 and 3e-18 at |r| = 1/4), then the n mod 4 quarter turns.  About half the
+// instructions of the library's sincospi, within a couple of units in the last place.
+#ifndef EIFP_SERIES_SINCOS
+#define EIFP_SERIES_SINCOS 1
+#endif
+__host__ __device__ inline void sincospi_series(double x, double* sn, double* cs) {
+    const double n = rint(2.0 * x);
+    const double r = fma(-0.5, n, x);
+    const double z = r * r;
+    // (-1)^k pi^(2k+1) / (2k+1)!, k = 8 .. 0
+    double ps = 7.952054001475513e-07;
+    ps = fma(ps, z, -2.1915353447830217e-05);
+    ps = fma(ps, z, 0.00046630280576761255);
+    ps = fma(ps, z, -0.0073704309457143504);
+    ps = fma(ps, z, 0.08214588661112823);
+    ps = fma(ps, z, -0.5992645293207921);
+    ps = fma(ps, z, 2.5501640398773455);
+    ps = fma(ps, z, -5.16771278004997);
+    ps = fma(ps, z, 3.141592653589793);
+    // (-1)^k pi^(2k) / (2k)!, k = 8 .. 0
+    double pc = 4.303069587032947e-06;
+    pc = fma(pc, z, -0.0001046381049248457);
+    pc = fma(pc, z, 0.0019295743094039231);
+    pc = fma(pc, z, -0.02580689139001406);
+    pc = fma(pc, z, 0.2353306303588932);
+    pc = fma(pc, z, -1.3352627688545895);
+    pc = fma(pc, z, 4.0587121264167685);
+    pc = fma(pc, z, -4.934802200544679);
+    pc = fma(pc, z, 1.0);
+    const double s = r * ps, c = pc;
+    const int q = (int)(n - 4.0 * floor(0.25 * n));  // n mod 4, exact
+    const double so = (q & 1) ? c : s, co = (q & 1) ? s : c;
+    *sn = q >= 2 ? -so : so;
+    *cs = (q == 1 || q == 2) ? -co : co;
+}
+
 // Propagate one mode in place.  b = (Omega_x, Omega_y, Omega_z).  With k = b/|b|,
 // theta = tau |b| / sqrt(mu eps), L(U) = k (k.U), X(U) = i k x U:
 //   H' = L(H) + cos(theta) (H - L(H)) - sin(theta) sqrt(eps/mu) X(E)
@@ -609,7 +648,8 @@ __device__ __forceinline__ void propagate_mode(cpx<T>* h, cpx<T>* e, double bx, 
     const double bn = b2 * ib;                      // |b|
     // the phase in half-turns, theta / pi, so that the reduction is exact for any tau
     double sn, cs;
-    sincospi(pp.tau_s_over_pi * bn, &sn, &cs);
+    if (EIFP_SERIES_SINCOS) sincospi_series(pp.tau_s_over_pi * bn, &sn, &cs);
+    else sincospi(pp.tau_s_over_pi * bn, &sn, &cs);
     if constexpr (sizeof(T) == 4 && EIFP_PROP_COMP) {
         // FP32: every coefficient of the transverse rotation (cos, sin, the unit wave
         // vector in the cross products) enters as a rounded part plus its remainder,

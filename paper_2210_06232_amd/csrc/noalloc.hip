@@ -62,6 +62,10 @@ eifp_status check_device_extent(const void* p, size_t need, const char* what) {
         (void)hipGetLastError();
         return fail(EIFP_ERR_INVALID_ARG, "%s is not device memory", what);
     }
+    int dev = -1;
+    EIFP_HIP_TRY(hipGetDevice(&dev));
+    if (at.type == hipMemoryTypeDevice && at.device != dev)
+        return fail(EIFP_ERR_INVALID_ARG, "%s is on device %d, the current device is %d", what, at.device, dev);
     hipDeviceptr_t base = nullptr;
     size_t size = 0;
     const hipError_t e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p);
