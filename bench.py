@@ -5,7 +5,8 @@ A step is one pass of the whole hot path over the state: forward 3-D FFT of the 
 field components (x R2C, z, y), the exact mode-wise propagator, the invariant partial
 sums, the inverse FFT (y, z, x C2R) and the deterministic invariant finalize.  The
 timed steps run as one call: between two steps the x inverse of one and the x forward
-of the next are one kernel (k_x_invfwd), which writes the physical state every step.
+of the next are one kernel (k_x_invfwd), which keeps the intermediate physical state in
+registers; the call's last step writes the state.
 
 Workload: 256^3 grid on [0,2pi] x [0,4pi] x [0,2pi], mu = eps = 1, tau = 0.1, seeded
 random divergence-free fields with spectrum (1+|k|^2)^-2 cut at |k| <= 42.67.  Fields
@@ -94,13 +95,13 @@ def summarize(prec: str, steps: int, wall: float, pass_ms: dict, inv: dict):
     tsize = 8 if prec == "fp64" else 4
     ms_per_step = 1e3 * wall / steps
     per_step = {k: v / steps for k, v in pass_ms.items()}
-    # algorithmic bytes: a pass reads and writes the state (6 components x N_S reals)
-    # once; the combined x kernel reads it once and writes it twice (physical field and
-    # spectrum).  Per step of the K timed steps: z forward, fused y and z inverse once;
-    # the x slots hold one x forward, K - 1 combined kernels and one x inverse.
+    # algorithmic bytes: every pass, the combined x kernel included, reads and writes the
+    # state (6 components x N_S reals) once.  Per step of the K timed steps: z forward,
+    # fused y and z inverse once; the x slots hold one x forward, K - 1 combined kernels
+    # and one x inverse.
     state = 6.0 * ns * tsize
     slot_bytes = {"x_fwd": 2 * state / steps, "z_fwd": 2 * state, "y_fused": 2 * state, "z_inv": 2 * state,
-                  "x_inv": (3 * (steps - 1) + 2) * state / steps}
+                  "x_inv": 2 * state}
     # the dominant kernel: the longest launch.  The z, fused and x-inverse slots have one
     # launch per step (the x-inverse slot's are the combined kernel but for the last), so
     # their time and bytes per step are per launch.

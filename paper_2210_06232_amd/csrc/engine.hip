@@ -70,8 +70,8 @@ eifp_status run_passes(const Engine& en, int mode, const void* md, int nm, hipSt
 
 // nsteps steps; steps n >= inv_from reduce the invariants.  With work != state, the x
 // inverse of each step but the last and the x forward of the step after it run as one
-// kernel (X_INVFWD), and the z forward pass after it takes the components in ascending
-// order.  Events per step as in run_passes
+// kernel (X_INVFWD, in place on work: the state buffer is written by the last step
+// only), and the z forward pass after it takes the components in ascending order.  Events per step as in run_passes
 // (the x forward slot is empty after the first step; the x inverse slot holds the
 // combined kernel).
 template <typename T>

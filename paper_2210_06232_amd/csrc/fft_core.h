@@ -508,6 +508,19 @@ struct LdsColsN {
 template <typename T> struct RowSkew { static constexpr int value = sizeof(T) == 8 ? EIFP_XSKEW64 : EIFP_XSKEW32; };
 template <typename T>
 __host__ __device__ constexpr int rows_pitch(int m) { return m + 1 + (RowSkew<T>::value ? m >> RowSkew<T>::value : 0); }
+// Ordering of LDS traffic that stays within one wave: a wave's LDS instructions are
+// performed in issue order, so a later read sees an earlier write of any lane of the
+// same wave once the compiler keeps them in program order (wavefront-scope fences and a
+// wave barrier; no instruction, no wait on other waves).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A row's T threads are consecutive and T divides 64, so each row lies within one wave
+// and its exchanges need only wave-scope ordering: the waves of a workgroup run their
+// rows independently.
 template <typename T, int LD>
 struct LdsRows {
     T* re;
@@ -519,13 +532,14 @@ struct LdsRows {
     }
     __device__ __forceinline__ void st(int pos, cpx<T> a) { re[p * LD + at(pos)] = a.x; im[p * LD + at(pos)] = a.y; }
     __device__ __forceinline__ cpx<T> ld(int pos) const { return {re[p * LD + at(pos)], im[p * LD + at(pos)]}; }
-    __device__ __forceinline__ void sync() { __syncthreads(); }
-    __device__ __forceinline__ void after_load() { __syncthreads(); }
+    __device__ __forceinline__ void sync() { wave_lds_sync(); }
+    __device__ __forceinline__ void after_load() { wave_lds_sync(); }
 };
 
 // Copy a twiddle table of n entries into LDS (all threads of the block take part).
-// The first FFT stage uses no twiddles and ends in a barrier, so no barrier is needed
-// between this copy and the first read.
+// Where the first FFT stage ends in a block barrier, no barrier is needed between this
+// copy and the first read; the row kernels, whose exchanges are wave-local, place one
+// after the copy.
 template <typename T>
 __device__ __forceinline__ void stage_table(cpx<T>* dst, const cpx<T>* __restrict__ src, int n) {
     // n entries, plus their lo parts for FP32 tables

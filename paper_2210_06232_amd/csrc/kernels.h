@@ -145,17 +145,18 @@ __device__ __forceinline__ void store_row(cpx<T>* out, const cpx<T> (&v)[P::E], 
 // Row helpers.  x_forward_row: v holds the row's M complex values (pairs of reals) at
 // positions t + T m_first(i); length-M FFT, then the split
 //   X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W^k (Z[k] - conj Z[M-k]),  W = exp(-2 pi i/Nx),
-// stored to out (X[0] + i X[M] in slot 0).  The LDS rows must be free (every earlier
-// read of them behind a barrier).
+// stored to out (X[0] + i X[M] in slot 0).  The row's LDS and the twiddle table are
+// ordered by the caller (the table staged behind a block barrier).
 template <typename T, class P, int LD>
 __device__ __forceinline__ void x_forward_row(cpx<T> (&v)[P::E], int t, LdsRows<T, LD>& lds, const cpx<T>* s_tw,
                                               cpx<T>* out, bool active) {
     constexpr int M = P::N, E = P::E, TT = P::T;
-    if constexpr (P::S == 1) __syncthreads();  // twiddle table visible before the split
+    static_assert(64 % TT == 0, "a row within one wave");
     fft_pencil<P, false, 2>(v, t, lds, s_tw);
+    lds.after_load();  // the row's last exchange read before it is written again
 #pragma unroll
     for (int i = 0; i < E; ++i) lds.st(t + TT * m_last<P>(i), v[i]);
-    __syncthreads();
+    lds.sync();
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int k = t + TT * m_last<P>(i);
@@ -179,9 +180,10 @@ __device__ __forceinline__ void x_forward_row(cpx<T> (&v)[P::E], int t, LdsRows<
 template <typename T, class P, int LD>
 __device__ __forceinline__ void x_inverse_row(cpx<T> (&v)[P::E], int t, LdsRows<T, LD>& lds, const cpx<T>* s_tw) {
     constexpr int M = P::N, E = P::E, TT = P::T;
+    static_assert(64 % TT == 0, "a row within one wave");
 #pragma unroll
     for (int i = 0; i < E; ++i) lds.st(t + TT * m_first<P>(i), v[i]);
-    __syncthreads();
+    lds.sync();
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int k = t + TT * m_first<P>(i);
@@ -193,7 +195,7 @@ __device__ __forceinline__ void x_inverse_row(cpx<T> (&v)[P::E], int t, LdsRows<
             v[i] = (x + xc) + muli(twmul<true>(s_tw, k, 2 * M, x - xc));
         }
     }
-    __syncthreads();
+    lds.after_load();
     fft_pencil<P, true, 2>(v, t, lds, s_tw);
 }
 
@@ -206,6 +208,7 @@ k_x_fwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
     __shared__ T s_im[NP * LD];
     __shared__ cpx<T> s_tw[2 * M * TwParts<T>::value];
     stage_table(s_tw, twx, 2 * M);
+    __syncthreads();  // the table, before any wave's first use
     const cpx<T>* src = md[blockIdx.y].state;
     cpx<T>* dst = md[blockIdx.y].work;
     const int t = threadIdx.x % TT, p = threadIdx.x / TT;
@@ -236,6 +239,7 @@ k_x_inv(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
     __shared__ T s_im[NP * LD];
     __shared__ cpx<T> s_tw[2 * M * TwParts<T>::value];
     stage_table(s_tw, twx, 2 * M);
+    __syncthreads();  // the table, before any wave's first use
     const cpx<T>* src = md[blockIdx.y].work;
     cpx<T>* dst = md[blockIdx.y].state;
     const int t = threadIdx.x % TT, p = threadIdx.x / TT;
@@ -251,14 +255,17 @@ k_x_inv(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
 }
 
 // Between two steps (work != state): the x inverse of one step and the x forward of the
-// next on the same row.  Reads work (the spectrum after the z inverse), writes the
-// physical row to state and its forward x transform back to work: the arithmetic of
-// k_x_inv followed by k_x_fwd, with one read of the state fewer.  Rows in the order of
-// k_x_inv, so the z forward pass after it takes the components in ascending order.
-// STREAM: the physical row is stored with the non-temporal hint; no pass before the
-// next step's combined kernel reads it, and for states larger than the last-level cache
-// this leaves the cache to the spectrum, which the z forward pass reads next.
-template <typename T, class P, int NP, bool STREAM>
+// next on the same row, in place on work (the spectrum after the z inverse).  The
+// physical row, the state after this step, lives only in registers: within one call
+// nothing reads an intermediate state (the invariants are summed in spectral space by
+// the fused pass), and the call's last step ends with k_x_inv, which writes the state.
+// The arithmetic is that of k_x_inv followed by k_x_fwd, with the physical row rounded
+// to T as a store would round it, so a call of K steps gives the bits of K calls of one
+// step, with one state read and one state write fewer per step.  Each row is read whole
+// (before the first exchange barrier) by the threads that later write it.  Rows in the
+// order of k_x_inv, so the z forward pass after it takes the components in ascending
+// order.
+template <typename T, class P, int NP>
 __global__ void __launch_bounds__(P::T * NP)
 k_x_invfwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restrict__ twx) {
     constexpr int M = P::N, E = P::E, TT = P::T, LD = rows_pitch<T>(M);
@@ -266,8 +273,8 @@ k_x_invfwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __res
     __shared__ T s_im[NP * LD];
     __shared__ cpx<T> s_tw[2 * M * TwParts<T>::value];
     stage_table(s_tw, twx, 2 * M);
+    __syncthreads();  // the table, before any wave's first use
     cpx<T>* work = md[blockIdx.y].work;
-    cpx<T>* state = md[blockIdx.y].state;
     const int t = threadIdx.x % TT, p = threadIdx.x / TT;
     const long row = x_inv_row(nrows, NP, p);
     const bool active = row >= 0 && row < nrows;
@@ -277,7 +284,12 @@ k_x_invfwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __res
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = in[t + TT * m_first<P>(i)];
     x_inverse_row<T, P, LD>(v, t, lds, s_tw);
-    store_row<T, P, true, STREAM>(state + row * M, v, t, active);
+    // the physical row as materialised values of T, as a store and a reload would give
+    // them: the empty asm keeps the compiler from merging the inverse's last operations
+    // with the forward's first ones (without it, FP64 rows differ in the last bit from
+    // those of k_x_inv followed by k_x_fwd)
+#pragma unroll
+    for (int i = 0; i < E; ++i) asm volatile("" : "+v"(v[i].x), "+v"(v[i].y));
     last_to_first<P>(v);
     x_forward_row<T, P, LD>(v, t, lds, s_tw, work + row * M, active);
 }

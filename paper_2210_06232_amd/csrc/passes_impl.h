@@ -32,9 +32,14 @@ constexpr int pow2floor(int a) {  // largest power of two <= a (a >= 1)
     return p;
 }
 
+// LDS budget of the x pass's row buffers per workgroup (rows of 2.3 KB in FP64 at
+// length 128: 21 rows, three workgroups per CU)
+#ifndef EIFP_XLDS_KB
+#define EIFP_XLDS_KB 48
+#endif
 template <typename T, int M> struct XCfg {
     using P = Plan<M, XYE<M>::E>;
-    static constexpr int NP = cmax(1, cmin(256 / P::T, (48 * 1024) / (rows_pitch<T>(M) * 2 * (int)sizeof(T))));
+    static constexpr int NP = cmax(1, cmin(256 / P::T, (EIFP_XLDS_KB * 1024) / (rows_pitch<T>(M) * 2 * (int)sizeof(T))));
 };
 
 // Row segment (bytes along x) of a tile of the single-component strided pass.
@@ -131,9 +136,8 @@ inline AxisGeom axis_geom(int axis, const Grid3& g) {
     return {(long)g.ny * g.M, (long)g.M, g.ny};
 }
 
-// Non-temporal stores of the physical field in the combined x kernel for states above
-// half of the 256 MB last-level cache (measured: 4% off a 256^3 FP64 step, 2% onto a
-// 128^3 one, whose whole state stays cached).
+// Non-temporal stores of the z passes for states above half of the 256 MB last-level
+// cache (a state that small stays cached from pass to pass).
 #ifndef EIFP_XSTREAM_MB
 #define EIFP_XSTREAM_MB 128
 #endif
@@ -150,12 +154,8 @@ int run_x(int kind, const Grid3& g, const void* md, int nm, const void* twx, hip
     const MemberDesc<T>* d = (const MemberDesc<T>*)md;
     if (kind == X_INV)
         hipLaunchKernelGGL((k_x_inv<T, typename C::P, C::NP>), grid, block, 0, st, d, nrows, (const cpx<T>*)twx);
-    else if (kind == X_INVFWD && stream_phys(g, sizeof(T)))
-        hipLaunchKernelGGL((k_x_invfwd<T, typename C::P, C::NP, true>), grid, block, 0, st, d, nrows,
-                           (const cpx<T>*)twx);
     else if (kind == X_INVFWD)
-        hipLaunchKernelGGL((k_x_invfwd<T, typename C::P, C::NP, false>), grid, block, 0, st, d, nrows,
-                           (const cpx<T>*)twx);
+        hipLaunchKernelGGL((k_x_invfwd<T, typename C::P, C::NP>), grid, block, 0, st, d, nrows, (const cpx<T>*)twx);
     else
         hipLaunchKernelGGL((k_x_fwd<T, typename C::P, C::NP>), grid, block, 0, st, d, nrows, (const cpx<T>*)twx);
     return check_launch();

@@ -12,6 +12,9 @@ not fit one pass):
 (`run --preset i [--inputs-cache DIR]` takes a named preset of workload.py instead, and
 `summarize ... OUT.json --note TEXT` writes elsewhere.)
 
+Shader-sequencer counters (instruction mix, issue and wait shares, LDS bank conflicts)
+take one run per group of SQ_PASSES, then `sq DIR1 DIR2 --out FILE.md`.
+
 `run` does a few FP64 and FP32 steps of the headline workload, then three plain device
 copies of a known size (the copy kernel calibrates the counters: its true traffic is
 the buffer size read plus the buffer size written).  `summarize` writes
@@ -127,6 +130,82 @@ def summarize(fetch_dir: str, write_dir: str, out_path: str = OUT_JSON, note=Non
     print(json.dumps(rec, indent=1))
 
 
+# Shader-sequencer counters of the step's kernels, one rocprofv3 pass per group (a pass
+# holds at most 8 SQ counters).
+SQ_PASSES = (
+    "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VMEM "
+    "SQ_WAIT_INST_ANY SQ_WAIT_ANY",
+    "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_SALU SQ_LDS_BANK_CONFLICT "
+    "SQ_WAIT_INST_LDS",
+)
+LDS_PER_CU = 160 * 1024
+
+
+def _waves_per_simd(wg: int, vgpr: int, agpr: int, lds: int) -> int:
+    """Resident waves per SIMD from the register and LDS footprint (512 registers per
+    lane per SIMD, VGPRs and AGPRs allocated together in blocks of 8; 160 KB of LDS per
+    CU; a workgroup's waves spread over the CU's 4 SIMDs)."""
+    regs = -(-(vgpr + agpr) // 8) * 8
+    by_regs = 512 // max(regs, 8)
+    wg_waves = -(-wg // 64)
+    by_lds = (LDS_PER_CU // lds) * wg_waves / 4 if lds else 8
+    return int(min(8, by_regs, by_lds))
+
+
+def sq_summary(dirs, out_path: str, title: str):
+    """Per kernel (name and template arguments) and precision: the SQ counters averaged
+    over its dispatches, per wave where they count instructions, with the footprint the
+    trace records (VGPRs, AGPRs, LDS) and the waves per SIMD it allows."""
+    vals, meta = {}, {}
+    for d in dirs:
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(fn) as f:
+                for r in csv.DictReader(f):
+                    name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("eifp::", "")
+                    if not name.startswith("k_") or name.startswith("k_twiddles"):
+                        continue
+                    vals.setdefault(name, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+                    meta[name] = (int(r["Workgroup_Size"]), int(r["VGPR_Count"]), int(r["Accum_VGPR_Count"]),
+                                  int(r["LDS_Block_Size"]))
+    avg = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in vals.items()}
+    lines = [f"# {title}", "",
+             "Counters averaged over each kernel's dispatches; per-wave figures divide by SQ_WAVES.",
+             "Cycle counters (SQ_*_CYCLES, SQ_ACTIVE_INST_*, SQ_WAIT_*) are in the sequencer's own",
+             "units; only their ratios are used: issue and wait shares of the waves' resident time",
+             "(SQ_WAVE_CYCLES).", "",
+             "| Kernel | WG | VGPR+AGPR | LDS (B) | waves/SIMD | waves | VALU/wave | LDS/wave | VMEM rd+wr/wave "
+             "| VALU share | LDS share | VMEM share | dependency wait | any wait | bank-conflict / LDS-active |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    rec = {}
+    for k in sorted(avg):
+        a = avg[k]
+        wg, vg, ag, lds = meta[k]
+        w = a.get("SQ_WAVES", 0.0)
+        wc = a.get("SQ_WAVE_CYCLES", 0.0)
+        per = lambda c: a[c] / w if w and c in a else None
+        share = lambda c: a[c] / wc if wc and c in a else None
+        vm = (per("SQ_INSTS_VMEM_RD") or 0.0) + (per("SQ_INSTS_VMEM_WR") or 0.0)
+        bc = a["SQ_LDS_BANK_CONFLICT"] / a["SQ_ACTIVE_INST_LDS"] if a.get("SQ_ACTIVE_INST_LDS") and \
+            "SQ_LDS_BANK_CONFLICT" in a else None
+        row = {"workgroup": wg, "vgpr": vg, "agpr": ag, "lds_bytes": lds,
+               "waves_per_simd": _waves_per_simd(wg, vg, ag, lds), "waves": w,
+               "valu_per_wave": per("SQ_INSTS_VALU"), "lds_per_wave": per("SQ_INSTS_LDS"), "vmem_per_wave": vm,
+               "valu_share": share("SQ_ACTIVE_INST_VALU"), "lds_share": share("SQ_ACTIVE_INST_LDS"),
+               "vmem_share": share("SQ_ACTIVE_INST_VMEM"), "dep_wait_share": share("SQ_WAIT_INST_ANY"),
+               "any_wait_share": share("SQ_WAIT_ANY"), "bank_conflict_per_lds_active": bc, "raw": a}
+        rec[k] = row
+        f = lambda x, p=3: "–" if x is None else (f"{x:.{p}f}" if isinstance(x, float) else str(x))
+        lines.append(f"| `{k}` | {wg} | {vg}+{ag} | {lds} | {row['waves_per_simd']} | {w:.0f} | "
+                     f"{f(row['valu_per_wave'], 0)} | {f(row['lds_per_wave'], 0)} | {f(vm, 0)} | "
+                     f"{f(row['valu_share'])} | {f(row['lds_share'])} | {f(row['vmem_share'])} | "
+                     f"{f(row['dep_wait_share'])} | {f(row['any_wait_share'])} | {f(bc)} |")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(os.path.splitext(out_path)[0] + ".json", "w") as f:
+        json.dump({"source_hash": kernel_source_hash(), "kernels": rec}, f, indent=1)
+    print("\n".join(lines))
+
+
 def main(argv):
     import argparse
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -140,9 +219,15 @@ def main(argv):
     m.add_argument("write_dir")
     m.add_argument("out", nargs="?", default=OUT_JSON)
     m.add_argument("--note", default=None)
+    q = sub.add_parser("sq", help="summarise SQ counter runs (one directory per pass of SQ_PASSES)")
+    q.add_argument("dirs", nargs="+")
+    q.add_argument("--out", required=True)
+    q.add_argument("--title", default="SQ counters of the step's kernels")
     a = ap.parse_args(argv)
     if a.cmd == "run":
         run(a.steps, a.preset, a.inputs_cache)
+    elif a.cmd == "sq":
+        sq_summary(a.dirs, a.out, a.title)
     else:
         summarize(a.fetch_dir, a.write_dir, a.out, a.note)
 

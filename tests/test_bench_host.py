@@ -27,10 +27,10 @@ def test_traffic_lookup_follows_the_source_hash(tmp_path, monkeypatch):
         return
     for prec, word in (("fp64", 8), ("fp32", 4)):
         state = 6 * 256 ** 3 * word
-        for k in ("k_c2c", "k_fused", "k_x_fwd", "k_x_inv"):
+        # every pass, the combined x kernel included, reads and writes the state once
+        for k in ("k_c2c", "k_fused", "k_x_fwd", "k_x_inv", "k_x_invfwd"):
             t = bench.measured_traffic(prec, k)
             assert t is not None and abs(t / (2 * state) - 1) < 0.05, (prec, k, t)
-        assert abs(bench.measured_traffic(prec, "k_x_invfwd") / (3 * state) - 1) < 0.05
     # a summary stamped with other sources is ignored
     stale = dict(rec, source_hash="0" * 16)
     (tmp_path / "profiles").mkdir()
@@ -56,3 +56,30 @@ def test_cpu_baseline_reports_one_thread_and_all_processes():
     assert out["kind"] == "oracle" and out["cores"] >= 1 and out["value"] > 0
     assert out["single_thread"]["cores"] == 1 and out["single_thread"]["value"] > 0
     assert "16^3" in out["sample"] and out["seconds"] > 0
+
+
+def test_sq_summary_reads_counter_csvs(tmp_path):
+    # two counter passes of one dispatch each, as rocprofv3 writes them
+    from paper_2210_06232_amd import profiling
+    hdr = ('"Correlation_Id","Dispatch_Id","Agent_Id","Queue_Id","Process_Id","Thread_Id","Grid_Size","Kernel_Id",'
+           '"Kernel_Name","Workgroup_Size","LDS_Block_Size","Scratch_Size","VGPR_Count","Accum_VGPR_Count",'
+           '"SGPR_Count","Counter_Name","Counter_Value","Start_Timestamp","End_Timestamp"\n')
+    name = '"void eifp::k_fused<double, eifp::Plan<256, 8>, 4, 0, 1>(int)"'
+    passes = {"p1": {"SQ_WAVES": 100, "SQ_WAVE_CYCLES": 1000, "SQ_ACTIVE_INST_VALU": 250, "SQ_ACTIVE_INST_LDS": 50,
+                     "SQ_WAIT_INST_ANY": 400},
+              "p2": {"SQ_WAVES": 100, "SQ_INSTS_VALU": 557200, "SQ_INSTS_LDS": 84100, "SQ_INSTS_VMEM_RD": 4800,
+                     "SQ_INSTS_VMEM_WR": 4800, "SQ_LDS_BANK_CONFLICT": 5}}
+    dirs = []
+    for d, cs in passes.items():
+        (tmp_path / d).mkdir()
+        rows = [f'1,1,"Agent 1",1,1,1,256,7,{name},128,78208,0,256,222,40,"{c}",{v},0,1\n' for c, v in cs.items()]
+        (tmp_path / d / "run_counter_collection.csv").write_text(hdr + "".join(rows))
+        dirs.append(str(tmp_path / d))
+    out = tmp_path / "sq.md"
+    profiling.sq_summary(dirs, str(out), "test")
+    rec = json.loads((tmp_path / "sq.json").read_text())["kernels"]
+    k = rec["k_fused<double, Plan<256, 8>, 4, 0, 1>"]
+    assert k["waves_per_simd"] == 1 and k["vgpr"] == 256 and k["agpr"] == 222
+    assert k["valu_per_wave"] == 5572 and k["lds_per_wave"] == 841 and k["vmem_per_wave"] == 96
+    assert k["valu_share"] == 0.25 and k["dep_wait_share"] == 0.4 and k["bank_conflict_per_lds_active"] == 0.1
+    assert "k_fused" in out.read_text()
