@@ -856,6 +856,13 @@ template <typename T, int N> struct ZLockstep {
     // workgroups per CU would not hold them)
     static constexpr int value = (N % 3 == 0 || N > 256) ? 1 : (sizeof(T) == 8 ? EIFP_ZLOCK64 : EIFP_ZLOCK32);
 };
+// Persistent fused pass: drain the vector memory counter between the last component
+// group's stores and its next-tile loads (256^3 FP64: fused pass 0.426-0.429 -> 0.419-0.420
+// ms; a drain after every group, or stores before loads in every group without it, are
+// slower; the split pass at 192^3 is unchanged by it and has none)
+#ifndef EIFP_FUSED_DRAIN
+#define EIFP_FUSED_DRAIN 1
+#endif
 template <typename T> struct ZPersist {
     static constexpr bool value = sizeof(T) == 8 ? EIFP_ZPERSIST64 != 0 : EIFP_ZPERSIST32 != 0;
 };
@@ -990,10 +997,25 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx, long 
                 lds.c = cq;
                 fft_stages_n<P, 0, true, kStagedTw, EIFP_FUSED_CT, NC>(
                     reinterpret_cast<cpx<T>(&)[NC][E]>(v[q]), tq, lds, s_tw);
+                if (EIFP_FUSED_DRAIN && q + NC == 6) {
+                    // last group: its stores, a wait until every outstanding vector memory
+                    // operation has completed, then its next-tile loads, so that the wait
+                    // for the next tile's data at the top of the loop covers loads only
 #pragma unroll
-                for (int n = 0; n < NC; ++n) {
-                    store_col<T, P, EIFP_FUSED_ST_AUX>(v[q + n], make_rsrc(buf + (q + n) * cs, cbytes), cur.voff, sstep, cur.active);
-                    if (more) load_col<T, P>(v[q + n], make_rsrc(src + (q + n) * cs, cbytes), nxt.voff, sstep);
+                    for (int n = 0; n < NC; ++n)
+                        store_col<T, P, EIFP_FUSED_ST_AUX>(v[q + n], make_rsrc(buf + (q + n) * cs, cbytes), cur.voff, sstep, cur.active);
+                    if (more) {
+                        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt and lgkmcnt not waited for
+#pragma unroll
+                        for (int n = 0; n < NC; ++n)
+                            load_col<T, P>(v[q + n], make_rsrc(src + (q + n) * cs, cbytes), nxt.voff, sstep);
+                    }
+                } else {
+#pragma unroll
+                    for (int n = 0; n < NC; ++n) {
+                        store_col<T, P, EIFP_FUSED_ST_AUX>(v[q + n], make_rsrc(buf + (q + n) * cs, cbytes), cur.voff, sstep, cur.active);
+                        if (more) load_col<T, P>(v[q + n], make_rsrc(src + (q + n) * cs, cbytes), nxt.voff, sstep);
+                    }
                 }
                 if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
             }
