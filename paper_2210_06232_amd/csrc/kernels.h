@@ -920,10 +920,12 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx, long 
         if (MODE != Z_JUMP) {
 #pragma unroll
             for (int q = 0; q < 6; q += NC) {
-                // re-derive the lane indices per group so that LDS addresses are
-                // recomputed (cheap ALU) instead of being kept live across all transforms
+                // FP64: re-derive the lane indices per group so that LDS addresses are
+                // recomputed (cheap ALU) instead of being kept live across all transforms;
+                // FP32, issue-bound with registers to spare, keeps them (5% fewer VALU
+                // instructions, the pass 2% faster at 256^3)
                 int tq = t, cq = c;
-                asm volatile("" : "+v"(tq), "+v"(cq));
+                if constexpr (sizeof(T) == 8) asm volatile("" : "+v"(tq), "+v"(cq));
                 lds.c = cq;
                 fft_stages_n<P, 0, false, kStagedTw, EIFP_FUSED_CT, NC>(
                     reinterpret_cast<cpx<T>(&)[NC][E]>(v[q]), tq, lds, s_tw);
@@ -993,7 +995,7 @@ k_fused(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx, long 
                 for (int n = 0; n < NC; ++n)
                     if (MODE == Z_STEP) last_to_first<P>(v[q + n]);
                 int tq = t, cq = c;
-                asm volatile("" : "+v"(tq), "+v"(cq));
+                if constexpr (sizeof(T) == 8) asm volatile("" : "+v"(tq), "+v"(cq));
                 lds.c = cq;
                 fft_stages_n<P, 0, true, kStagedTw, EIFP_FUSED_CT, NC>(
                     reinterpret_cast<cpx<T>(&)[NC][E]>(v[q]), tq, lds, s_tw);
@@ -1228,7 +1230,7 @@ k_fused_split(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx,
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 int tq = t, cq = c;
-                asm volatile("" : "+v"(tq), "+v"(cq));
+                if constexpr (sizeof(T) == 8) asm volatile("" : "+v"(tq), "+v"(cq));  // as in k_fused
                 lds.c = cq;
                 fft_pencil<P, false, kStagedTw, EIFP_FUSED_CT>(v[q], tq, lds, s_tw);
                 if (EIFP_FUSED_SB & 1) __builtin_amdgcn_sched_barrier(0);
@@ -1261,7 +1263,7 @@ k_fused_split(const MemberDesc<T>* __restrict__ md, int M, int n_outer, int ntx,
             for (int q = 0; q < 3; ++q) {
                 if (MODE == Z_STEP) last_to_first<P>(v[q]);
                 int tq = t, cq = c;
-                asm volatile("" : "+v"(tq), "+v"(cq));
+                if constexpr (sizeof(T) == 8) asm volatile("" : "+v"(tq), "+v"(cq));  // as in k_fused
                 lds.c = cq;
                 fft_pencil<P, true, kStagedTw, EIFP_FUSED_CT>(v[q], tq, lds, s_tw);
                 store_col<T, P, EIFP_FUSED_ST_AUX>(v[q], make_rsrc(own + q * cs, cbytes), cur.voff, sstep, cur.active);
