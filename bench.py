@@ -59,6 +59,32 @@ def measured_traffic(prec: str, kernel: str):
         return None
 
 
+# Vector-ALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD every
+# 4 cycles (16 lanes per clock, the FP64 and non-packed FP32 rate behind the 78.6 TFLOP/s
+# FP64 vector peak: 256 x 4 x 16 x 2 flop x 2.4 GHz), at 2.4 GHz.
+PEAK_VALU_GIPS = 256 * 4 * 2.4e9 / 4 / 1e9
+
+
+def measured_valu(prec: str, kernel: str):
+    """VALU wave-instructions per launch of the step's `kernel` from the committed SQ
+    counter summary, if it was taken on the current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "step_256cubed_sq_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        if rec.get("source_hash") != kernel_source_hash():
+            return None
+        ctype = "double" if prec == "fp64" else "float"
+        for name, ent in rec["kernels"].items():
+            if name.startswith(f"{kernel}<{ctype},"):
+                return float(ent["raw"]["SQ_INSTS_VALU"])
+    except (KeyError, ValueError, TypeError):
+        return None
+    return None
+
+
 def timed_steps(s, steps: int):
     """K steps of the headline workload on solver s, timed; returns (wall s, pass ms)."""
     import torch
@@ -114,6 +140,15 @@ def summarize(prec: str, steps: int, wall: float, pass_ms: dict, inv: dict):
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": KERNEL_NAMES[dominant], "pass": dominant,
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(avg_ms, 5)}
+    # the same launch against the vector-ALU issue ceiling (instructions per launch from
+    # the committed SQ counters of the same kernel sources)
+    valu = measured_valu(prec, KERNEL_NAMES[dominant])
+    issue = None
+    if valu is not None:
+        gips = valu / (avg_ms * 1e-3) / 1e9
+        issue = {"bound": "alu", "achieved": round(gips, 1), "peak": PEAK_VALU_GIPS,
+                 "unit": "G VALU wave-instructions/s", "frac": round(gips / PEAK_VALU_GIPS, 4),
+                 "kernel": KERNEL_NAMES[dominant], "valu_per_launch": valu}
     step_bytes = sum(slot_bytes.values())
     value = ns / (ms_per_step * 1e-3)
     # the step's HBM bytes as the counters count them (committed summary of the same
@@ -130,6 +165,7 @@ def summarize(prec: str, steps: int, wall: float, pass_ms: dict, inv: dict):
         "ms_per_step": ms_per_step,
         "pass_ms_per_step": {k: round(v, 5) for k, v in per_step.items()},
         "roofline": roofline,
+        "issue": issue,
         "step_alg_bytes": step_bytes,
         "step_hbm_gbs": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
         # HBM traffic of the step by the counters, and its fraction of the 8 TB/s peak
@@ -292,6 +328,9 @@ def main():
         "data": "synthetic",
         "config": WORKLOAD,
         "roofline": r64["roofline"],
+        # the dominant kernel against the vector-ALU issue ceiling (null while the SQ
+        # counter summary was taken on other kernel sources)
+        "issue": r64["issue"],
         "cpu_baseline": cpu,
         # attainable bandwidth (plain copy of the FP64 state) and the method's irreducible
         # traffic fraction (12 words per point-step) against the 8 TB/s peak
@@ -304,7 +343,7 @@ def main():
                              "last-level cache (MALL) included; gfx950 exposes no counter below the L2",
         "pass_ms_per_step": r64["pass_ms_per_step"],
         "fp32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
-                 "roofline": r32["roofline"], "pass_ms_per_step": r32["pass_ms_per_step"],
+                 "roofline": r32["roofline"], "issue": r32["issue"], "pass_ms_per_step": r32["pass_ms_per_step"],
                  "method_alg_frac": r32["method_alg_frac"], "step_hbm_gbs": r32["step_hbm_gbs"],
                  "step_counted_gbs": r32["step_counted_gbs"], "step_counted_frac": r32["step_counted_frac"]},
         "serving": serve,

@@ -83,3 +83,24 @@ def test_sq_summary_reads_counter_csvs(tmp_path):
     assert k["valu_per_wave"] == 5572 and k["lds_per_wave"] == 841 and k["vmem_per_wave"] == 96
     assert k["valu_share"] == 0.25 and k["dep_wait_share"] == 0.4 and k["bank_conflict_per_lds_active"] == 0.1
     assert "k_fused" in out.read_text()
+
+
+def test_issue_roofline_follows_the_sq_summary(tmp_path, monkeypatch):
+    import bench
+    with open(os.path.join(ROOT, "profiles", "step_256cubed_sq_counters.json")) as f:
+        rec = json.load(f)
+    if rec["source_hash"] == bench.kernel_source_hash():
+        # one launch of the 256^3 fused pass issues tens of millions of wave instructions
+        for prec in ("fp64", "fp32"):
+            v = bench.measured_valu(prec, "k_fused")
+            assert v is not None and 1e7 < v < 1e9, (prec, v)
+        r = bench.summarize("fp32", 20, 0.015, {"x_fwd": 0.2, "z_fwd": 2.6, "y_fused": 5.0, "z_inv": 2.5,
+                                                  "x_inv": 3.5, "finalize": 0.1}, {"energy": 1.0})
+        assert r["issue"]["bound"] == "alu" and r["issue"]["kernel"] == "k_fused"
+        assert abs(r["issue"]["achieved"] - bench.measured_valu("fp32", "k_fused") / 0.25e-3 / 1e9) < 0.1
+        assert r["issue"]["peak"] == 614.4
+    stale = dict(rec, source_hash="0" * 16)
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "step_256cubed_sq_counters.json").write_text(json.dumps(stale))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_valu("fp64", "k_fused") is None
