@@ -110,8 +110,12 @@ eifp_status eifp_init(eifp_solver **out, int nx, int ny, int nz, const eifp_doma
 /* Enqueue nsteps time steps of size tau (Alg. 2 with t_end = tau, repeated): forward
  * 3-D transform, exact propagator, inverse transform, invariant reduction.  tau may
  * be negative or arbitrarily large (the scheme has no step-size restriction, Thm 3.4).
- * Returns after enqueueing; the work runs on the solver's stream.  nsteps = 0 is a
- * no-op.  Errors: INVALID_ARG (NULL solver, non-finite tau, nsteps < 0), DEVICE. */
+ * Returns after enqueueing; the work runs on the solver's stream.  The fields after the
+ * last step are what eifp_fields reads; the intermediate states of one call are formed
+ * (with the same rounding as separate calls: n steps in one call and n calls of one step
+ * give the same bits) but not stored, and after a DEVICE error the fields and invariants
+ * are undefined.  nsteps = 0 is a no-op.  Errors: INVALID_ARG (NULL solver, non-finite
+ * tau, nsteps < 0), DEVICE. */
 eifp_status eifp_step(eifp_solver *s, double tau, long long nsteps);
 
 /* Anchor: store the spectrum of the current state (its forward 3-D transform, Def. 2.3

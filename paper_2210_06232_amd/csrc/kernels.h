@@ -17,7 +17,9 @@
 //            inverse C2C along y.  Powers of two: one thread holds all six components
 //            (k_fused; persistent workgroups in FP64, components transformed in pairs);
 //            lengths with a factor 3: two thread groups hold H and E (k_fused_split).
-//   z^-1, x^-1 as above in reverse (complex-to-real merge back).
+//   z^-1, x^-1 as above in reverse (complex-to-real merge back).  Between two steps of
+//            one call, x^-1 and the next x pass are one kernel (k_x_invfwd) that keeps
+//            the physical row in registers: a call writes the state once, at its end.
 //
 // Every kernel works on a batch of solves of one shape ("members"): the member index
 // comes from the grid and selects a descriptor (buffers and per-solve scalars) from a
