@@ -44,12 +44,37 @@ OUT_JSON = os.path.join(ROOT, "profiles", "traffic_256cubed.json")
 KERNEL_SOURCES = ("fft_core.h", "kernels.h", "passes.h", "passes_impl.h", "passes_f64.hip", "passes_f32.hip")
 
 
+def code_text(src: str) -> str:
+    """The source with comments removed and whitespace runs collapsed: what the hash of
+    the kernel sources covers, so that editing a comment does not mark the counters
+    taken on the same code as stale."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif src[i] == '"':  # string literal (asm templates): copied whole
+            j = i + 1
+            while j < n and src[j] != '"':
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(src[i])
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2210_06232_amd", "csrc")
     for name in KERNEL_SOURCES:
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
+            h.update(name.encode() + code_text(f.read()).encode())
     return h.hexdigest()[:16]
 
 

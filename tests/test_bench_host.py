@@ -104,3 +104,12 @@ def test_issue_roofline_follows_the_sq_summary(tmp_path, monkeypatch):
     (tmp_path / "profiles" / "step_256cubed_sq_counters.json").write_text(json.dumps(stale))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_valu("fp64", "k_fused") is None
+
+
+def test_kernel_hash_ignores_comments_and_whitespace():
+    from paper_2210_06232_amd.profiling import code_text
+    a = 'int f(int x) {  // twice\n  return 2 * x; /* doubled */ }\nasm volatile("" : "+v"(x));'
+    b = 'int f(int x) {\n    return 2 * x;   }\n// a note\nasm volatile("" : "+v"(x));'
+    assert code_text(a) == code_text(b)
+    assert code_text(a) != code_text(a.replace("2 * x", "3 * x"))
+    assert code_text('s = "//not a comment";') == 's = "//not a comment";'
