@@ -97,17 +97,16 @@ __device__ __forceinline__ float swap_lane_pair(float x) {
     return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
 }
 
-// Store a row held as v[i] at positions t + T m(i) (m = m_last if LAST, else m_first),
-// optionally with the non-temporal hint.  With 8-byte elements and 8 threads per row a
-// store instruction would cover half of each 128-byte line of the row, and the two
-// halves would reach memory separately; instead lanes t and t ^ 1 trade one value so
-// that each lane stores two adjacent elements (16 bytes) and one instruction covers
-// blocks m and m + 1 (m even) of the row: whole lines.
-template <typename T, class P, bool LAST, bool STREAM = false>
+// Store a row held as v[i] at positions t + T m(i) (m = m_last if LAST, else m_first).
+// With 8-byte elements and 8 threads per row a store instruction would cover half of
+// each 128-byte line of the row, and the two halves would reach memory separately;
+// instead lanes t and t ^ 1 trade one value so that each lane stores two adjacent
+// elements (16 bytes) and one instruction covers blocks m and m + 1 (m even) of the row:
+// whole lines.
+template <typename T, class P, bool LAST>
 __device__ __forceinline__ void store_row(cpx<T>* out, const cpx<T> (&v)[P::E], int t, bool active) {
     constexpr int E = P::E, TT = P::T;
     typedef T quad_t __attribute__((ext_vector_type(4)));
-    typedef T pair_t __attribute__((ext_vector_type(2)));
     if constexpr (sizeof(T) == 4 && TT == 8 && E % 2 == 0) {
         const bool odd = t & 1;
 #pragma unroll
@@ -123,24 +122,11 @@ __device__ __forceinline__ void store_row(cpx<T>* out, const cpx<T> (&v)[P::E], 
             q.y = lo.y;
             q.z = hi.x;
             q.w = hi.y;
-            if (active) {
-                if constexpr (STREAM) __builtin_nontemporal_store(q, reinterpret_cast<quad_t*>(out + pos));
-                else *reinterpret_cast<quad_t*>(out + pos) = q;
-            }
+            if (active) *reinterpret_cast<quad_t*>(out + pos) = q;
         }
     } else if (active) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            cpx<T>* d = out + t + TT * (LAST ? m_last<P>(i) : m_first<P>(i));
-            if constexpr (STREAM) {
-                pair_t u;
-                u.x = v[i].x;
-                u.y = v[i].y;
-                __builtin_nontemporal_store(u, reinterpret_cast<pair_t*>(d));
-            } else {
-                *d = v[i];
-            }
-        }
+        for (int i = 0; i < E; ++i) out[t + TT * (LAST ? m_last<P>(i) : m_first<P>(i))] = v[i];
     }
 }
 

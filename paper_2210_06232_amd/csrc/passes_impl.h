@@ -138,11 +138,11 @@ inline AxisGeom axis_geom(int axis, const Grid3& g) {
 
 // Non-temporal stores of the z passes for states above half of the 256 MB last-level
 // cache (a state that small stays cached from pass to pass).
-#ifndef EIFP_XSTREAM_MB
-#define EIFP_XSTREAM_MB 128
+#ifndef EIFP_NT_STATE_MB
+#define EIFP_NT_STATE_MB 128
 #endif
-inline bool stream_phys(const Grid3& g, size_t tsize) {
-    return 6.0 * g.nx * g.ny * g.nz * (double)tsize > EIFP_XSTREAM_MB * 1048576.0;
+inline bool nt_state(const Grid3& g, size_t tsize) {
+    return 6.0 * g.nx * g.ny * g.nz * (double)tsize > EIFP_NT_STATE_MB * 1048576.0;
 }
 
 template <typename T, int M>
@@ -171,7 +171,7 @@ int run_c2c(bool inv, int axis, const Grid3& g, const void* md, int nm, const vo
     const dim3 block(C::P::T * C::B);
     const MemberDesc<T>* d = (const MemberDesc<T>*)md;
     // large states: non-temporal stores (see kStoreNT)
-    const bool nt = stream_phys(g, sizeof(T));
+    const bool nt = nt_state(g, sizeof(T));
     if (inv && nt)
         hipLaunchKernelGGL((k_c2c<T, typename C::P, C::B, true, kStoreNT>), grid, block, 0, st, d, g.M, a.pstride,
                            a.ostride, g.cs(), (const cpx<T>*)tw, fin_nparts, 0);
