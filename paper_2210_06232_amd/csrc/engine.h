@@ -53,7 +53,8 @@ struct Engine {
     void* twx = nullptr;
     void* twy = nullptr;
     void* twz = nullptr;
-    int nparts = 0;  // partial records per member
+    int nparts = 0;  // partial records per member written by the fused pass
+    int nrec = 0;    // record capacity of a member's partials buffer (partial_capacity)
     long long bytes = 0;
 
     // allocate the tables and form them on the device (enqueued on stream, which is then
@@ -62,7 +63,7 @@ struct Engine {
     void release();
     size_t state_bytes() const { return (size_t)6 * (size_t)ns * tsize; }
     // room for the extended record (INV_XPART doubles per workgroup)
-    size_t partial_bytes() const { return (size_t)nparts * INV_XPART * sizeof(double); }
+    size_t partial_bytes() const { return (size_t)nrec * INV_XPART * sizeof(double); }
 
     // One step (mode Z_STEP: x, z, fused y, z^-1 with the finalize, x^-1) or a forward-only
     // evaluation of the invariants (mode Z_FORWARD, or Z_FORWARD_EXT for the extended
@@ -84,6 +85,12 @@ struct Engine {
     // with the invariants if want_inv.
     eifp_status jump(const void* md, int nm, hipStream_t st, bool want_inv = true) const;
 };
+
+// Partial records a member's buffer must hold for grid g: those of the fused pass, or
+// one per packed x column when the grid steps with the plane pass, whichever is more
+// (-1: unsupported size).
+template <typename T>
+int partial_capacity(const Grid3& g);
 
 // Bytes of the twiddle table of length n: n entries exp(-2 pi i k / n), plus their
 // rounding remainders for FP32 tables.

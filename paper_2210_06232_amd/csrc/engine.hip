@@ -39,10 +39,61 @@ eifp_status rc_to_status(int rc, const char* what) {
     return fail(EIFP_ERR_DEVICE, "%s: kernel launch failed: %s", what, hipGetErrorString(hipGetLastError()));
 }
 
+// Grids whose (y, z) plane fits in LDS step with the plane pass in place of the z
+// forward, fused y and z inverse passes (the partial records it writes, one per packed
+// x column, must fit the member's partials buffer, which every caller sizes for
+// partial_capacity records); the x kernel after it finalizes.
+template <typename T>
+bool use_plane(const Engine& en) {
+    return plane_ok<T>(en.g) && en.g.M <= en.nrec;
+}
+
+}  // namespace
+
+template <typename T>
+int partial_capacity(const Grid3& g) {
+    const int n = fused_partial_count<T>(AXIS_Y, g);
+    if (n <= 0) return -1;
+    return plane_ok<T>(g) && g.M > n ? g.M : n;
+}
+template int partial_capacity<double>(const Grid3&);
+template int partial_capacity<float>(const Grid3&);
+
+namespace {
+
+// The middle of a plane step, between the x forward and the x inverse: events 2, 3, 4
+// (the z slots empty, the fused slot holding the plane pass).
+template <typename T>
+eifp_status run_plane_middle(const Engine& en, const void* md, int nm, hipStream_t st, hipEvent_t* ev,
+                             bool want_inv) {
+    int rc;
+    if (ev) EIFP_HIP_TRY(hipEventRecord(ev[2], st));
+    if ((rc = launch_plane<T>(en.g, md, nm, en.twy, en.twz, want_inv ? 1 : 0, st))) return rc_to_status(rc, "plane pass");
+    if (ev) {
+        EIFP_HIP_TRY(hipEventRecord(ev[3], st));
+        EIFP_HIP_TRY(hipEventRecord(ev[4], st));
+    }
+    return EIFP_OK;
+}
+
 template <typename T>
 eifp_status run_passes(const Engine& en, int mode, const void* md, int nm, hipStream_t st, hipEvent_t* ev,
                        bool want_inv) {
     int rc;
+    if (mode == Z_STEP && use_plane<T>(en)) {
+        if (ev) EIFP_HIP_TRY(hipEventRecord(ev[0], st));
+        if ((rc = launch_x<T>(X_FWD, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x forward");
+        if (ev) EIFP_HIP_TRY(hipEventRecord(ev[1], st));
+        eifp_status s = run_plane_middle<T>(en, md, nm, st, ev, want_inv);
+        if (s) return s;
+        if ((rc = launch_x<T>(X_INV, en.g, md, nm, en.twx, st, want_inv ? en.g.M : 0)))
+            return rc_to_status(rc, "x inverse");
+        if (ev) {
+            EIFP_HIP_TRY(hipEventRecord(ev[5], st));
+            EIFP_HIP_TRY(hipEventRecord(ev[6], st));
+        }
+        return EIFP_OK;
+    }
     if (ev) EIFP_HIP_TRY(hipEventRecord(ev[0], st));
     if ((rc = launch_x<T>(X_FWD, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x forward");
     if (ev) EIFP_HIP_TRY(hipEventRecord(ev[1], st));
@@ -71,13 +122,15 @@ eifp_status run_passes(const Engine& en, int mode, const void* md, int nm, hipSt
 // nsteps steps; steps n >= inv_from reduce the invariants.  With work != state, the x
 // inverse of each step but the last and the x forward of the step after it run as one
 // kernel (X_INVFWD, in place on work: the state buffer is written by the last step
-// only), and the z forward pass after it takes the components in ascending order.  Events per step as in run_passes
-// (the x forward slot is empty after the first step; the x inverse slot holds the
-// combined kernel).
+// only), and the z forward pass after it takes the components in ascending order.
+// Events per step as in run_passes (the x forward slot is empty after the first step;
+// the x inverse slot holds the combined kernel).  Grids with a plane pass run it in
+// place of the three middle passes (use_plane).
 template <typename T>
 eifp_status run_steps(const Engine& en, const void* md, int nm, long long nsteps, hipStream_t st, hipEvent_t* ev,
                       long long inv_from, bool combine_x) {
     int rc;
+    const bool plane = use_plane<T>(en);
     for (long long n = 0; n < nsteps; ++n) {
         const bool want_inv = n >= inv_from;
         hipEvent_t* e = ev ? ev + 7 * n : nullptr;
@@ -85,6 +138,17 @@ eifp_status run_steps(const Engine& en, const void* md, int nm, long long nsteps
         if (e) EIFP_HIP_TRY(hipEventRecord(e[0], st));
         if (first && (rc = launch_x<T>(X_FWD, en.g, md, nm, en.twx, st))) return rc_to_status(rc, "x forward");
         if (e) EIFP_HIP_TRY(hipEventRecord(e[1], st));
+        if (plane) {
+            eifp_status s = run_plane_middle<T>(en, md, nm, st, e, want_inv);
+            if (s) return s;
+            if ((rc = launch_x<T>(last ? X_INV : X_INVFWD, en.g, md, nm, en.twx, st, want_inv ? en.g.M : 0)))
+                return rc_to_status(rc, "x inverse");
+            if (e) {
+                EIFP_HIP_TRY(hipEventRecord(e[5], st));
+                EIFP_HIP_TRY(hipEventRecord(e[6], st));
+            }
+            continue;
+        }
         if ((rc = launch_c2c<T>(false, AXIS_Z, en.g, md, nm, en.twz, st, 0, first ? 1 : 0)))
             return rc_to_status(rc, "z forward");
         if (e) EIFP_HIP_TRY(hipEventRecord(e[2], st));
@@ -199,6 +263,7 @@ eifp_status Engine::init(int nx, int ny, int nz, eifp_precision p, hipStream_t s
     ns = (long long)nx * ny * nz;
     nparts = p == EIFP_FP64 ? fused_partial_count<double>(AXIS_Y, g) : fused_partial_count<float>(AXIS_Y, g);
     if (nparts <= 0) return fail(EIFP_ERR_UNSUPPORTED_SIZE, "no compiled plan for ny = %d", ny);
+    nrec = p == EIFP_FP64 ? partial_capacity<double>(g) : partial_capacity<float>(g);
     eifp_status st = EIFP_OK;
     if (p == EIFP_FP64) {
         if ((st = make_table<double>(&twx, nx, &bytes, stream)) || (st = make_table<double>(&twy, ny, &bytes, stream)) ||

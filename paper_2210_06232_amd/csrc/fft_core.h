@@ -22,12 +22,19 @@ struct alignas(2 * sizeof(T)) cpx {
 
 template <typename T> __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T> __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+// a b + c in one rounding.  Sums of two products below are written with it explicitly:
+// under contraction the compiler would pick which of the two products to round first,
+// and could pick differently in different kernels, so that the same transform written
+// in two kernels (the x inverse and forward, alone and combined) would differ in the
+// last bit.
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <typename T> __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
-    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+    return {fmat(a.x, b.x, -(a.y * b.y)), fmat(a.x, b.y, a.y * b.x)};
 }
 // a * conj(b)
 template <typename T> __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
-    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+    return {fmat(a.x, b.x, a.y * b.y), fmat(a.y, b.x, -(a.x * b.y))};
 }
 template <typename T> __device__ __forceinline__ cpx<T> conj(cpx<T> a) { return {a.x, -a.y}; }
 
@@ -61,7 +68,7 @@ __device__ __forceinline__ cpx<T> twmul(const cpx<T>* tw, int k, int n, cpx<T> v
 template <typename T>
 __device__ __forceinline__ cpx<T> rotc(double c, double s, cpx<T> v) {
     if constexpr (sizeof(T) == 8) {
-        return {v.x * c - v.y * s, v.x * s + v.y * c};
+        return {fmat(v.x, c, -(v.y * s)), fmat(v.x, s, v.y * c)};
     } else {
         const float ch = (float)c, sh = (float)s;
         const float cl = (float)(c - (double)ch), sl = (float)(s - (double)sh);

@@ -218,10 +218,10 @@ __device__ __forceinline__ long x_inv_row(long nrows, int np, int p) {
     return EIFP_MALL_ORDER ? nrows - 1 - r : r;
 }
 
-// Inverse reads work, writes state.
+// Inverse reads work, writes state.  (The body is shared with k_x_inv_fin.)
 template <typename T, class P, int NP>
-__global__ void __launch_bounds__(P::T * NP)
-k_x_inv(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restrict__ twx) {
+__device__ __forceinline__ void x_inv_body(const MemberDesc<T>* __restrict__ md, long nrows,
+                                           const cpx<T>* __restrict__ twx) {
     constexpr int M = P::N, E = P::E, TT = P::T, LD = rows_pitch<T>(M);
     __shared__ T s_re[NP * LD];
     __shared__ T s_im[NP * LD];
@@ -241,6 +241,11 @@ k_x_inv(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
     x_inverse_row<T, P, LD>(v, t, lds, s_tw);
     store_row<T, P, true>(dst + row * M, v, t, active);
 }
+template <typename T, class P, int NP>
+__global__ void __launch_bounds__(P::T * NP)
+k_x_inv(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restrict__ twx) {
+    x_inv_body<T, P, NP>(md, nrows, twx);
+}
 
 // Between two steps (work != state): the x inverse of one step and the x forward of the
 // next on the same row, in place on work (the spectrum after the z inverse).  The
@@ -252,10 +257,10 @@ k_x_inv(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restri
 // step, with one state read and one state write fewer per step.  Each row is read whole
 // (before the first exchange barrier) by the threads that later write it.  Rows in the
 // order of k_x_inv, so the z forward pass after it takes the components in ascending
-// order.
+// order.  (The body is shared with k_x_invfwd_fin.)
 template <typename T, class P, int NP>
-__global__ void __launch_bounds__(P::T * NP)
-k_x_invfwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restrict__ twx) {
+__device__ __forceinline__ void x_invfwd_body(const MemberDesc<T>* __restrict__ md, long nrows,
+                                              const cpx<T>* __restrict__ twx) {
     constexpr int M = P::N, E = P::E, TT = P::T, LD = rows_pitch<T>(M);
     __shared__ T s_re[NP * LD];
     __shared__ T s_im[NP * LD];
@@ -280,6 +285,11 @@ k_x_invfwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __res
     for (int i = 0; i < E; ++i) asm volatile("" : "+v"(v[i].x), "+v"(v[i].y));
     last_to_first<P>(v);
     x_forward_row<T, P, LD>(v, t, lds, s_tw, work + row * M, active);
+}
+template <typename T, class P, int NP>
+__global__ void __launch_bounds__(P::T * NP)
+k_x_invfwd(const MemberDesc<T>* __restrict__ md, long nrows, const cpx<T>* __restrict__ twx) {
+    x_invfwd_body<T, P, NP>(md, nrows, twx);
 }
 
 // ---------------------------------------------------------------------------------

@@ -126,7 +126,8 @@ eifp_status step_noalloc(void* fields, int nx, int ny, int nz, const eifp_domain
     en.ns = (long long)nx * ny * nz;
     en.nparts = fused_partial_count<T>(AXIS_Y, en.g);
     if (en.nparts <= 0) return fail(EIFP_ERR_UNSUPPORTED_SIZE, "no compiled plan for ny = %d", ny);
-    const Layout L = layout<T>(nx, ny, nz, en.nparts);
+    en.nrec = partial_capacity<T>(en.g);
+    const Layout L = layout<T>(nx, ny, nz, en.nrec);
     if (L.end > kScratchBytes)
         return fail(EIFP_ERR_UNSUPPORTED_SIZE, "grid %dx%dx%d needs %zu bytes of scratch; the fixed array holds %zu", nx,
                     ny, nz, L.end, kScratchBytes);

@@ -5,7 +5,8 @@
 // Pass order of one step: x forward (R2C split, rows), z forward (C2C, single component),
 // fused y (forward, propagator, invariant partials, inverse; all six components),
 // z inverse (with the invariant finalize), x inverse (C2R merge); between two steps the
-// x inverse and the next x forward run as one kernel.  The fused pass runs along y
+// x inverse and the next x forward run as one kernel.  Grids whose (y, z) plane fits in
+// LDS run the three middle passes as one plane pass.  The fused pass runs along y
 // because its pencils are then M complex elements apart, while the strided z axis is
 // handled by the single-component pass, which can use wide tiles.
 //
@@ -28,10 +29,23 @@ struct Grid3 {
 };
 
 // x pass: X_FWD (state -> work), X_INV (work -> state), or X_INVFWD (between two steps
-// with work != state: the inverse into state and the next step's forward back into work)
+// with work != state: the inverse and the next step's forward, in place on work)
 enum XKind { X_FWD = 0, X_INV = 1, X_INVFWD = 2 };
+// fin_nparts > 0 (X_INV and X_INVFWD only): one extra workgroup per member also
+// finalizes that many invariant partial records (those of a preceding plane pass)
 template <typename T>
-int launch_x(int kind, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st);
+int launch_x(int kind, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st, int fin_nparts = 0);
+
+// Small grids: the plane pass (z forward, y forward, propagator and invariant partials,
+// y inverse, z inverse) of one step, one workgroup per packed x column, whose (Ny, Nz)
+// plane of the six components is held in LDS; it writes g.M partial records per member
+// (want_inv), which the x kernel after it finalizes.  plane_ok: the grid has a compiled
+// plane pass (kUnsupported from launch_plane otherwise).
+template <typename T>
+bool plane_ok(const Grid3& g);
+template <typename T>
+int launch_plane(const Grid3& g, const void* md, int nm, const void* twy, const void* twz, int want_inv,
+                 hipStream_t st);
 
 // single-component C2C along y or z on each member's work buffer (six components, in
 // place); fin_nparts > 0 also finalizes each member's invariant partials (that many

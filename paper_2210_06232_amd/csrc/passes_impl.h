@@ -2,6 +2,7 @@
 // Included once per precision (passes_f64.hip, passes_f32.hip).
 #pragma once
 #include "passes.h"
+#include "small_plane.h"
 
 namespace eifp {
 
@@ -146,12 +147,24 @@ inline bool nt_state(const Grid3& g, size_t tsize) {
 }
 
 template <typename T, int M>
-int run_x(int kind, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st) {
+int run_x(int kind, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st, int fin_nparts) {
     using C = XCfg<T, M>;
     const long nrows = 6L * g.nz * g.ny;
-    const dim3 grid((unsigned)((nrows + C::NP - 1) / C::NP), (unsigned)nm);
+    const unsigned nblk = (unsigned)((nrows + C::NP - 1) / C::NP);
+    const dim3 grid(nblk, (unsigned)nm);
     const dim3 block(C::P::T * C::NP);
     const MemberDesc<T>* d = (const MemberDesc<T>*)md;
+    if (fin_nparts > 0) {  // one more workgroup per member: the finalize
+        if (kind == X_INV)
+            hipLaunchKernelGGL((k_x_inv_fin<T, typename C::P, C::NP>), dim3(nblk + 1, nm), block, 0, st, d, nrows,
+                               (const cpx<T>*)twx, fin_nparts);
+        else if (kind == X_INVFWD)
+            hipLaunchKernelGGL((k_x_invfwd_fin<T, typename C::P, C::NP>), dim3(nblk + 1, nm), block, 0, st, d,
+                               nrows, (const cpx<T>*)twx, fin_nparts);
+        else
+            return kUnsupported;
+        return check_launch();
+    }
     if (kind == X_INV)
         hipLaunchKernelGGL((k_x_inv<T, typename C::P, C::NP>), grid, block, 0, st, d, nrows, (const cpx<T>*)twx);
     else if (kind == X_INVFWD)
@@ -282,11 +295,11 @@ int count_fused(int axis, const Grid3& g) {
 inline int axis_len(int axis, const Grid3& g) { return axis == AXIS_Y ? g.ny : g.nz; }
 
 template <typename T>
-int launch_x(int kind, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st) {
+int launch_x(int kind, const Grid3& g, const void* md, int nm, const void* twx, hipStream_t st, int fin_nparts) {
     switch (g.M) {
 #define EIFP_CASE(MM) \
     case MM:          \
-        return run_x<T, MM>(kind, g, md, nm, twx, st);
+        return run_x<T, MM>(kind, g, md, nm, twx, st, fin_nparts);
         EIFP_HALF_SIZES(EIFP_CASE)
 #undef EIFP_CASE
         default:
@@ -335,6 +348,72 @@ int fused_partial_count(int axis, const Grid3& g) {
     }
 }
 
+// plane pass: pencil lengths with a single-thread plan, and a plane of the six
+// components within the LDS budget (below two workgroups' worth at FP64 32 x 32)
+#ifndef EIFP_PLANE_SIZES
+#define EIFP_PLANE_SIZES(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32)
+#endif
+// 0 switches the plane pass off (every grid takes the strided passes)
+#ifndef EIFP_PLANE
+#define EIFP_PLANE 1
+#endif
+inline bool plane_len(int n) {
+    switch (n) {
+#define EIFP_CASE(N) \
+    case N:          \
+        return true;
+        EIFP_PLANE_SIZES(EIFP_CASE)
+#undef EIFP_CASE
+        default:
+            return false;
+    }
+}
+// Plane pass only where it is the faster path: planes of up to 576 points, where a
+// step is dominated by the per-launch cost (us per FP64 step, plane / strided: 8^3 9.7 /
+// 21.6, 16^3 13.7 / 25.2, 256 x 16^2 22.5 / 33.6, 32 x 16 x 32 23.0 / 29.0, 24^3 23.9 /
+// 24.6).  A 32 x 32 plane is 13% slower than the strided passes: its workgroup takes a
+// whole CU and only M of them run.
+#ifndef EIFP_PLANE_MAX_POINTS
+#define EIFP_PLANE_MAX_POINTS 576
+#endif
+template <typename T>
+bool plane_ok(const Grid3& g) {
+    return EIFP_PLANE && plane_len(g.ny) && plane_len(g.nz) && g.ny * g.nz <= EIFP_PLANE_MAX_POINTS &&
+           6L * g.ny * g.nz * (long)sizeof(cpx<T>) <= 96L * 1024;
+}
+template <typename T, int NY, int NZ>
+int run_plane(const Grid3& g, const void* md, int nm, const void* twy, const void* twz, int want_inv, hipStream_t st) {
+    hipLaunchKernelGGL((k_yz_plane<T, NY, NZ>), dim3((unsigned)g.M, (unsigned)nm), dim3(kPlaneThreads), 0, st,
+                       (const MemberDesc<T>*)md, g.M, g.cs(), (const cpx<T>*)twy, (const cpx<T>*)twz, want_inv);
+    return check_launch();
+}
+template <typename T, int NY>
+int run_plane_z(const Grid3& g, const void* md, int nm, const void* twy, const void* twz, int want_inv, hipStream_t st) {
+    switch (g.nz) {
+#define EIFP_CASE(N) \
+    case N:          \
+        return run_plane<T, NY, N>(g, md, nm, twy, twz, want_inv, st);
+        EIFP_PLANE_SIZES(EIFP_CASE)
+#undef EIFP_CASE
+        default:
+            return kUnsupported;
+    }
+}
+template <typename T>
+int launch_plane(const Grid3& g, const void* md, int nm, const void* twy, const void* twz, int want_inv,
+                 hipStream_t st) {
+    if (!plane_ok<T>(g)) return kUnsupported;
+    switch (g.ny) {
+#define EIFP_CASE(N) \
+    case N:          \
+        return run_plane_z<T, N>(g, md, nm, twy, twz, want_inv, st);
+        EIFP_PLANE_SIZES(EIFP_CASE)
+#undef EIFP_CASE
+        default:
+            return kUnsupported;
+    }
+}
+
 template <typename T>
 int launch_finalize(const void* md, int nm, int nparts, hipStream_t st, bool extended) {
     if (extended)
@@ -345,7 +424,9 @@ int launch_finalize(const void* md, int nm, int nparts, hipStream_t st, bool ext
 }
 
 #define EIFP_INSTANTIATE(T)                                                                                   \
-    template int launch_x<T>(int, const Grid3&, const void*, int, const void*, hipStream_t);                  \
+    template int launch_x<T>(int, const Grid3&, const void*, int, const void*, hipStream_t, int);             \
+    template bool plane_ok<T>(const Grid3&);                                                                 \
+    template int launch_plane<T>(const Grid3&, const void*, int, const void*, const void*, int, hipStream_t); \
     template int launch_c2c<T>(bool, int, const Grid3&, const void*, int, const void*, hipStream_t, int, int); \
     template int launch_fused<T>(int, int, const Grid3&, const void*, int, const void*, int, hipStream_t);    \
     template int fused_partial_count<T>(int, const Grid3&);                                                   \

@@ -108,9 +108,10 @@ long long state_bytes_of(int nx, int ny, int nz, int prec) {
     return 6LL * nx * ny * nz * (prec == EIFP_FP64 ? 8 : 4);
 }
 
+// partial records per member (the capacity the engine's passes need)
 int nparts_of(const Key& k) {
     const Grid3 g{k.nx, k.ny, k.nz, k.nx / 2};
-    return k.prec == EIFP_FP64 ? fused_partial_count<double>(AXIS_Y, g) : fused_partial_count<float>(AXIS_Y, g);
+    return k.prec == EIFP_FP64 ? partial_capacity<double>(g) : partial_capacity<float>(g);
 }
 
 long long group_bytes_of(const Key& k, int max_batch) {
@@ -208,7 +209,7 @@ eifp_status group_alloc(Group* g, int max_batch) {
     EIFP_HIP_TRY(hipEventCreate(&g->ev1));
     eifp_status st = g->en.init(g->key.nx, g->key.ny, g->key.nz, (eifp_precision)g->key.prec, g->st);
     if (st) return st;
-    g->nparts = g->en.nparts;
+    g->nparts = g->en.nrec;
     const size_t pb = (size_t)max_batch * g->nparts * INV_NPART * sizeof(double);
     if (hipMalloc((void**)&g->partials, pb) != hipSuccess || hipMalloc((void**)&g->inv_dev, max_batch * 64) != hipSuccess ||
         hipMalloc(&g->desc_dev, 2 * max_batch * sizeof(DescImage)) != hipSuccess) {

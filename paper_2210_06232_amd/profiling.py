@@ -41,7 +41,8 @@ OUT_JSON = os.path.join(ROOT, "profiles", "traffic_256cubed.json")
 
 
 # the sources that define the step's kernels and their launch shapes
-KERNEL_SOURCES = ("fft_core.h", "kernels.h", "passes.h", "passes_impl.h", "passes_f64.hip", "passes_f32.hip")
+KERNEL_SOURCES = ("fft_core.h", "kernels.h", "small_plane.h", "passes.h", "passes_impl.h", "passes_f64.hip",
+                  "passes_f32.hip")
 
 
 def code_text(src: str) -> str:

@@ -156,10 +156,12 @@ def test_invariants_bitwise_deterministic():
 
 # Between two steps of one call the x inverse and the next x forward run as one kernel;
 # the arithmetic is that of separate calls, so n steps in one call and n calls of one
-# step give the same bits.  (256, 256, 64) FP64 is above the state size where the
-# combined kernel stores the physical field with the non-temporal hint.
+# step give the same bits.  The FP64 shapes take x plans of one, two and four threads per
+# row (half lengths 16, 32, 64, 48 and 128), whose radix-16 and radix-12 stages multiply
+# by in-register rotations.
 @pytest.mark.parametrize("shape,prec", [((32, 48, 16), "fp64"), ((64, 64, 64), "fp32"), ((24, 12, 48), "fp32"),
-                                        ((256, 256, 64), "fp64")])
+                                        ((256, 256, 64), "fp64"), ((64, 64, 64), "fp64"), ((128, 48, 32), "fp64"),
+                                        ((96, 24, 48), "fp64")])
 def test_multi_step_call_equals_single_steps_bitwise(shape, prec):
     m = eifp()
     H, E = inputs.random_fields(shape, DOMAIN, workload=4, p=2.0)
