@@ -23,11 +23,11 @@ pytestmark = pytest.mark.gpu
 TOL = {"fp64": 1e-12, "fp32": 2e-6}
 DOMAIN = (0.0, 2 * math.pi, -1.0, 4 * math.pi - 1.0, 0.5, 2.5)
 # every pencil length of the plane pass (4 ... 32, with the factor-3 lengths) along y and
-# along z, in planes of at most 16 x 16 points (the pass is taken up to 576 points),
-# small and wide in x; the widest columns (M = 128) run more workgroups than the fused
-# pass has partial records
+# along z, small and wide in x, up to the largest planes it takes (576 points: 24 x 24,
+# and 16 x 32 with the longest z pencils); the widest columns (M = 128) run more
+# workgroups than the fused pass has partial records
 PLANE_SHAPES = [(4, 4, 4), (16, 16, 16), (6, 12, 8), (64, 16, 16), (8, 32, 8), (16, 4, 32), (24, 8, 24),
-                (12, 6, 24), (256, 8, 8), (32, 4, 16), (8, 24, 6)]
+                (12, 6, 24), (256, 8, 8), (32, 4, 16), (8, 24, 6), (8, 24, 24), (6, 16, 32)]
 
 
 def eifp():
