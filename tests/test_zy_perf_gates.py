@@ -1,8 +1,9 @@
 """Performance regression gates on the 256^3 headline grid: the step time of both forms
-and the bandwidth of the fused pass, with ~30% margin over what one MI355X measures
-(FP64 1.46 ms per step, fused pass 3.8 TB/s; FP32 0.76 ms, 3.1 TB/s), so that a slow
-path (a kernel falling back to a worse configuration, a lost fusion) fails here rather
-than only in the benchmark.  Inputs are white noise: the time does not depend on them."""
+and the bandwidth of the fused pass, with 30-40% margin over what one MI355X measures
+(FP64 1.33-1.35 ms per step, fused pass 3.8 TB/s; FP32 0.70-0.71 ms, 3.3 TB/s), so that
+a slow path (a kernel falling back to a worse configuration, a lost fusion) fails here
+rather than only in the benchmark.  Inputs are white noise: the time does not depend on
+them."""
 import math
 import time
 
