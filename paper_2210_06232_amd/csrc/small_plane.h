@@ -120,8 +120,8 @@ k_yz_plane(const MemberDesc<T>* __restrict__ md, int M, long cs, const cpx<T>* _
 
 // The member's basic invariant record from its nparts partial records, by the first wave
 // of a workgroup alone (no barrier, so any block size will do): per-lane compensated
-// sums over records lane, lane + 64, ..., then a fixed butterfly across the lanes; the
-// same outputs as finalize_member.
+// sums over records lane, lane + 64, ..., then a fixed butterfly across the lanes.  It
+// writes the record finalize_member writes, its sums taken in another fixed order.
 __device__ __forceinline__ void finalize_member_wave(const double* __restrict__ partials, int nparts,
                                                      double* __restrict__ out) {
     if (threadIdx.x >= 64) return;
