@@ -19,7 +19,10 @@ request arriving at once (throughput), each beside serial FP64 solves of the sam
 stream.
 
 Prints ONE JSON line.  ``value`` is FP64 field-point-steps/s; the FP32 form is timed on
-the same input and reported under ``"fp32"``; serving under ``"serving"``.
+the same input and reported under ``"fp32"``; serving under ``"serving"``.  The same K
+FP64 steps as a caller holding the fields in host memory sees them (init from host
+arrays, the steps, the fields back to host arrays) are reported under ``"host_to_host"``,
+beside ``value``, never as it.
 """
 from __future__ import annotations
 
@@ -113,6 +116,28 @@ def run_gpu_pair(H, E, steps: int, warmup: int):
         t32 = timed_steps(s32, steps)
         inv64, inv32 = s64.invariants(), s32.invariants()
     return summarize("fp64", steps, *t64, inv64), summarize("fp32", steps, *t32, inv32)
+
+
+def host_to_host(H, E, steps: int):
+    """K FP64 steps from host arrays to host arrays: eifp_init (allocation, the
+    non-finite check, upload and relayout), the steps, eifp_fields (download and
+    relayout), timed from the host with the device idle before and synchronised after."""
+    import torch
+    from paper_2210_06232_amd import eifp
+    nx, ny, nz = WORKLOAD["grid"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with eifp.Solver(H, E, WORKLOAD["domain"], WORKLOAD["mu"], WORKLOAD["eps"], "fp64") as s:
+        s.sync()
+        t1 = time.perf_counter()
+        s.step(WORKLOAD["tau"], steps)
+        s.sync()
+        t2 = time.perf_counter()
+        s.fields()
+        t3 = time.perf_counter()
+    return {"value": nx * ny * nz * steps / (t3 - t0), "unit": "field-point-steps/s", "steps": steps,
+            "dtype": "f64", "init_s": round(t1 - t0, 4), "steps_s": round(t2 - t1, 4),
+            "fields_s": round(t3 - t2, 4)}
 
 
 def summarize(prec: str, steps: int, wall: float, pass_ms: dict, inv: dict):
@@ -305,6 +330,9 @@ def main():
     r64, r32 = run_gpu_pair(H, E, args.steps, args.warmup)
     print(f"[bench] fp64 {r64['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
     print(f"[bench] fp32 {r32['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
+    h2h = host_to_host(H, E, args.steps)
+    print(f"[bench] fp64 host to host {h2h['value']:.3e} field-point-steps/s "
+          f"(init {h2h['init_s']} s, fields {h2h['fields_s']} s)", file=sys.stderr, flush=True)
     nx, ny, nz = WORKLOAD["grid"]
     copy = copy_ceiling(6 * nx * ny * nz * 8)
     print(f"[bench] plain copy {copy['gbs']} GB/s", file=sys.stderr, flush=True)
@@ -342,6 +370,8 @@ def main():
         "step_counted_note": "FETCH_SIZE/WRITE_SIZE count L2-to-fabric traffic, reads served by the 256 MB "
                              "last-level cache (MALL) included; gfx950 exposes no counter below the L2",
         "pass_ms_per_step": r64["pass_ms_per_step"],
+        # the same K FP64 steps with the upload from and the download to host arrays
+        "host_to_host": h2h,
         "fp32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
                  "roofline": r32["roofline"], "issue": r32["issue"], "pass_ms_per_step": r32["pass_ms_per_step"],
                  "method_alg_frac": r32["method_alg_frac"], "step_hbm_gbs": r32["step_hbm_gbs"],
