@@ -423,11 +423,15 @@ int launch_finalize(const void* md, int nm, int nparts, hipStream_t st, bool ext
     return check_launch();
 }
 
+// The strided single-component passes are instantiated in translation units of their own
+// (passes_c2c_f64.hip, passes_c2c_f32.hip), which the build compiles with a scheduling
+// strategy that measured faster for them alone.
+#define EIFP_INSTANTIATE_C2C(T) \
+    template int launch_c2c<T>(bool, int, const Grid3&, const void*, int, const void*, hipStream_t, int, int);
 #define EIFP_INSTANTIATE(T)                                                                                   \
     template int launch_x<T>(int, const Grid3&, const void*, int, const void*, hipStream_t, int);             \
     template bool plane_ok<T>(const Grid3&);                                                                 \
     template int launch_plane<T>(const Grid3&, const void*, int, const void*, const void*, int, hipStream_t); \
-    template int launch_c2c<T>(bool, int, const Grid3&, const void*, int, const void*, hipStream_t, int, int); \
     template int launch_fused<T>(int, int, const Grid3&, const void*, int, const void*, int, hipStream_t);    \
     template int fused_partial_count<T>(int, const Grid3&);                                                   \
     template int launch_finalize<T>(const void*, int, int, hipStream_t, bool);

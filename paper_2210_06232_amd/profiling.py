@@ -42,7 +42,7 @@ OUT_JSON = os.path.join(ROOT, "profiles", "traffic_256cubed.json")
 
 # the sources that define the step's kernels and their launch shapes
 KERNEL_SOURCES = ("fft_core.h", "kernels.h", "small_plane.h", "passes.h", "passes_impl.h", "passes_f64.hip",
-                  "passes_f32.hip")
+                  "passes_f32.hip", "passes_c2c_f64.hip", "passes_c2c_f32.hip")
 
 
 def code_text(src: str) -> str:
@@ -73,9 +73,11 @@ def code_text(src: str) -> str:
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2210_06232_amd", "csrc")
+    from paper_2210_06232_amd.build import FILE_FLAGS  # per-source compiler flags change the code too
     for name in KERNEL_SOURCES:
         with open(os.path.join(csrc, name), encoding="utf-8") as f:
             h.update(name.encode() + code_text(f.read()).encode())
+        h.update(" ".join(FILE_FLAGS.get(name, [])).encode())
     return h.hexdigest()[:16]
 
 
