@@ -113,3 +113,14 @@ def test_kernel_hash_ignores_comments_and_whitespace():
     assert code_text(a) == code_text(b)
     assert code_text(a) != code_text(a.replace("2 * x", "3 * x"))
     assert code_text('s = "//not a comment";') == 's = "//not a comment";'
+
+
+def test_kernel_hash_covers_per_source_compiler_flags(monkeypatch):
+    # a source's extra compiler flags change its code, so they change the hash that
+    # decides whether committed counter summaries still describe the built kernels
+    from paper_2210_06232_amd import build, profiling
+    h0 = profiling.kernel_source_hash()
+    flags = dict(build.FILE_FLAGS)
+    flags["passes_c2c_f64.hip"] = []
+    monkeypatch.setattr(build, "FILE_FLAGS", flags)
+    assert profiling.kernel_source_hash() != h0
